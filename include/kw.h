@@ -1,0 +1,203 @@
+/*
+ * kw.h -- C ABI of the MI355X (gfx950) k-space pseudospectral solver.
+ *
+ * One simulation advances the coupled first-order equations of
+ * Jaros, Rendell & Treeby (Section 2.2): the spectral pressure gradient and
+ * velocity update, Eqs. (4a)-(4b); the spectral velocity divergence and split
+ * density update with the nonlinear denominator, Eqs. (4c)-(4d); the
+ * equation of state with the B/A term, Eq. (6); and the power-law absorption
+ * and dispersion terms through fractional Laplacians, Eq. (8).  Wavenumbers
+ * follow Eq. (5); the k-space correction is kappa = sinc(c_ref k dt / 2).
+ * The split-field PML (Section 2.2) is applied inside the grid.
+ *
+ * Every step runs on the GPU: 3D real-to-complex / complex-to-real FFTs made of
+ * hand-written HIP passes, with the element-wise updates fused into them.
+ * There is no host round trip inside kw_step.
+ *
+ * Conventions
+ *   - Grid point (x, y, z) has the flat index x + nx*(y + ny*z) (x fastest).
+ *   - Host arrays passed to kw_create / kw_set_field are copied before the call
+ *     returns; the caller keeps ownership of them.
+ *   - The device workspace is owned by the caller (typically a torch uint8
+ *     tensor); the library borrows it from kw_create until kw_destroy and
+ *     carves every device array out of it.  The library allocates no device
+ *     memory of its own (kw_create and kw_gather use no hipMalloc).
+ *   - All device work is enqueued on the stream given to kw_create
+ *     (a hipStream_t passed as void*; NULL is the default stream).
+ *   - Every function returns a status code; on failure kw_last_error() gives a
+ *     thread-local message.  Nothing aborts and no exception crosses the ABI.
+ *   - One thread may use a simulation at a time.  Simulations on different
+ *     streams may run concurrently.
+ */
+#ifndef KW_H
+#define KW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define KW_OK            0
+#define KW_EINVAL       -1   /* bad argument, NULL pointer, out-of-range value          */
+#define KW_EUNSUPPORTED -2   /* a dimension is not 2^a 3^b 5^c, too small/large, odd nx */
+#define KW_ENOMEM       -3   /* workspace smaller than kw_workspace_size()              */
+#define KW_EDEVICE      -4   /* HIP error (no device, launch failure, ...)              */
+#define KW_ESTATE       -5   /* call not valid in the current state                     */
+#define KW_ENONFINITE   -6   /* a NaN or Inf appeared in the pressure (see kw_stats)     */
+
+/* medium flags */
+#define KW_NONLINEAR     1u  /* B/A term of Eq. (6) and denominator of Eq. (4d)        */
+#define KW_ABSORBING     2u  /* absorption and dispersion term L_d, Eq. (8)             */
+
+/* recorded quantities (kw_sensor.record) and gather targets (kw_gather.what) */
+#define KW_REC_P_MAX     1u  /* running maximum of p over recorded steps               */
+#define KW_REC_P_RMS     2u  /* sqrt(mean p^2) over recorded steps                     */
+#define KW_REC_P_SERIES  4u  /* p at the sensor points, one row per recorded step      */
+#define KW_REC_P_FINAL   8u  /* p on the whole grid after the last step                */
+#define KW_REC_U_FINAL  16u  /* ux, uy, uz (staggered) after the last step, 3 fields   */
+#define KW_REC_INTENSITY 32u /* time-mean p^2 / (rho0 c0) at the sensor points         */
+
+/* fields for kw_set_field / kw_gather_field (whole grid, float32) */
+#define KW_FIELD_P       1   /* acoustic pressure p^n                                  */
+#define KW_FIELD_UX      2   /* particle velocity u_x^(n-1/2) at x + dx/2              */
+#define KW_FIELD_UY      3
+#define KW_FIELD_UZ      4
+#define KW_FIELD_RHOX    5   /* split acoustic density rho_x^n                          */
+#define KW_FIELD_RHOY    6
+#define KW_FIELD_RHOZ    7
+
+typedef struct kw_sim kw_sim;
+
+typedef struct kw_grid {
+    int32_t nx, ny, nz;       /* points; nx even; every size of the form 2^a 3^b 5^c,
+                                 4 <= n <= 1024 (nx <= 2048)                          */
+    double  dx, dy, dz;       /* spacing [m], > 0                                       */
+    double  dt;               /* time step [s]; 0 -> cfl * min(dx,dy,dz) / max(c0)     */
+    double  cfl;              /* used when dt == 0                                      */
+    int32_t pml_size[3];      /* PML points per side along x, y, z (inside the grid)   */
+    double  pml_alpha[3];     /* PML strength [Np per grid point]                      */
+} kw_grid;
+
+/* Each property is either a host array of nx*ny*nz floats or, when the
+ * pointer is NULL, the scalar next to it.  alpha0 is the power-law prefactor
+ * in dB / (MHz^y cm), converted internally to Np (rad/s)^-y m^-1 as stated
+ * with Eq. (3).  tau and eta follow Eq. (3). */
+typedef struct kw_medium {
+    const float *c0;      double c0_scalar;       /* sound speed [m/s]            */
+    const float *rho0;    double rho0_scalar;     /* ambient density [kg/m^3]     */
+    const float *alpha0;  double alpha0_scalar;   /* dB / (MHz^y cm)              */
+    const float *bona;    double bona_scalar;     /* nonlinearity parameter B/A   */
+    double   alpha_power;                         /* y, 0 < y < 3, y != 1         */
+    double   c_ref;                               /* kappa reference; 0 -> max c0 */
+    uint32_t flags;                               /* KW_NONLINEAR | KW_ABSORBING  */
+} kw_medium;
+
+/* Pressure drive s_e(t) [Pa] of each element, injected at the listed grid
+ * points as an additive mass source split evenly over the three density
+ * components (M_xi = 2 s / (3 c0 dx)) at t = (n + 1/2) dt, Eq. (4d).
+ * s_e = amp[e] sin(2 pi freq t + phase[e]), or signal[e * n_samples + n]
+ * when signal is non-NULL (0 after the last sample). */
+typedef struct kw_source {
+    int64_t        n_points;     /* 0 -> no source                                 */
+    const int64_t *index;        /* flat indices, strictly increasing               */
+    const int32_t *element;      /* element of each point; NULL -> all element 0   */
+    int32_t        n_elements;   /* >= 1 when n_points > 0                          */
+    const float   *amp;          /* [n_elements] Pa                                 */
+    const float   *phase;        /* [n_elements] rad                                */
+    double         freq;         /* Hz                                              */
+    const float   *signal;       /* optional [n_elements * n_samples]               */
+    int32_t        n_samples;
+} kw_source;
+
+/* Sensor: quantities in `record` are kept for the points in `index` (strictly
+ * increasing) or for every grid point when index == NULL (n_points ignored).
+ * The pressure p^(n) after step n is recorded when n >= record_start (>= 1). */
+typedef struct kw_sensor {
+    uint32_t       record;
+    int64_t        n_points;
+    const int64_t *index;
+    int32_t        record_start;
+    int32_t        series_capacity;   /* rows kept for KW_REC_P_SERIES */
+} kw_sensor;
+
+typedef struct kw_stats_t {
+    int64_t steps;             /* steps taken                                        */
+    int64_t nonfinite_step;    /* first step with a NaN/Inf pressure, -1 if none     */
+    double  dt;                /* time step used [s]                                  */
+    double  c_ref;             /* reference sound speed used [m/s]                    */
+    int64_t workspace_bytes;   /* bytes of the workspace actually used                */
+    int32_t fft_forward_per_step;  /* 3D forward transforms per step (Section 3.4)   */
+    int32_t fft_inverse_per_step;  /* 3D inverse transforms per step                  */
+    int32_t kernels_per_step;      /* kernel launches per step                        */
+    int32_t n_classes;             /* kernel classes with timing below                */
+    char    class_name[16][24];    /* kernel class names                              */
+    double  class_ms[16];          /* summed device time per class (profiling on)     */
+    int64_t class_launches[16];    /* launches per class while profiling              */
+    double  class_bytes[16];       /* algorithmic HBM bytes per launch of the class   */
+} kw_stats_t;
+
+/* Device bytes needed by a simulation with these inputs (the same number is
+ * the admission footprint of the serving layer).  0 when the inputs are
+ * invalid (kw_last_error says why). */
+size_t kw_workspace_size(const kw_grid *grid, const kw_medium *medium,
+                         const kw_source *source, const kw_sensor *sensor);
+
+/* Validate the inputs (before any device call), precompute the 1D operator
+ * tables and per-point medium coefficients in float64 on the host, carve the
+ * workspace, upload, and zero the state (p = u = rho = 0).  `source` and
+ * `sensor` may be NULL.  On success *out owns host-side state only. */
+int kw_create(const kw_grid *grid, const kw_medium *medium, const kw_source *source,
+              const kw_sensor *sensor, void *dev_workspace, size_t ws_bytes,
+              void *stream, kw_sim **out);
+
+/* Enqueue n >= 0 time steps on the simulation's stream and return. */
+int kw_step(kw_sim *sim, int32_t n);
+
+/* Copy a recorded quantity (one KW_REC_* bit) into dst, as float32:
+ *   P_MAX, P_RMS, INTENSITY: one value per sensor point (or grid point);
+ *   P_SERIES: rows x sensor points, rows = min(recorded steps, capacity);
+ *   P_FINAL: nx*ny*nz values; U_FINAL: 3*nx*ny*nz values (ux, uy, uz).
+ * dst is device memory when dst_is_device != 0, else host memory.  The call
+ * synchronizes the stream; it fails with KW_EINVAL when dst_bytes is too
+ * small (the needed size is reported by kw_gather_bytes) and returns
+ * KW_ENONFINITE (after copying) when a NaN/Inf pressure was detected. */
+int kw_gather(kw_sim *sim, uint32_t what, void *dst, size_t dst_bytes, int dst_is_device);
+int64_t kw_gather_bytes(kw_sim *sim, uint32_t what);
+
+/* Overwrite one state field (KW_FIELD_*) with nx*ny*nz float32 values from
+ * host (src_is_device == 0) or device memory.  Setting the pressure does not
+ * touch the density components; initial-value problems set both. */
+int kw_set_field(kw_sim *sim, int field, const void *src, int src_is_device);
+/* Read one state field (KW_FIELD_*) into dst (nx*ny*nz float32). */
+int kw_gather_field(kw_sim *sim, int field, void *dst, int dst_is_device);
+
+/* Per-kernel-class device timing with HIP events around every launch on the
+ * simulation's stream (off by default; launches are eager while it is on). */
+int kw_profile(kw_sim *sim, int on);
+int kw_stats(kw_sim *sim, kw_stats_t *out);
+
+/* Use captured HIP graphs of `steps_per_graph` steps for kw_step (0 = off,
+ * the default is 8). */
+int kw_set_graph(kw_sim *sim, int32_t steps_per_graph);
+
+/* Override the FFT radix schedule of one axis (0 = x, 1 = y, 2 = z) and the
+ * column-tile width of the y/z passes.  radices lists the factors of the
+ * transform length in forward order (product must equal the length: nx/2 for
+ * x).  Used by the autotuner; must be called before the first kw_step. */
+int kw_set_plan(kw_sim *sim, int axis, const int32_t *radices, int32_t n_radices,
+                int32_t tile);
+
+/* Free library-owned host state (never the workspace).  NULL-safe. */
+int kw_destroy(kw_sim *sim);
+
+/* Thread-local message describing the last failure. */
+const char *kw_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KW_H */

@@ -1,0 +1,153 @@
+// Internal structures shared by the host engine (engine.cpp) and the HIP
+// kernels (kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace kw {
+
+constexpr int kMaxPasses = 8;
+
+// Radix schedule of one 1D transform.  Passes run in the listed order; the
+// inverse transform of an axis uses the same factors in reverse order so that
+// the last inverse pass and the first forward pass share one register layout
+// (that is what lets an inverse FFT, an element-wise update and a forward FFT
+// run back to back without an LDS exchange in between).
+struct FftPlan {
+    int n;                    // transform length (complex points)
+    int np;                   // number of passes
+    int L;                    // threads per transform = max over passes of n / radix
+    int rmax;                 // largest radix
+    int radix[kMaxPasses];
+};
+
+// One real field or spectrum array plus an optional per-point map: when
+// `map` is null the scalar is used everywhere.
+struct Coef {
+    const float *map;
+    float scalar;
+};
+
+struct GridDev {
+    int nx, ny, nz;          // real grid
+    int M;                   // nx / 2: complex points per packed half-spectrum row
+    int rows;                // ny * nz
+    float inv_n;             // 1 / (nx ny nz)
+    float half_cdt;          // c_ref * dt / 2 (argument scale of kappa)
+    float dt;
+    float y_tau;             // (y - 2) / 2, exponent of k^2 for k^(y-2)
+    float y_eta;             // (y - 1) / 2
+};
+
+// 1D tables (device), float32 copies of float64 host values.
+struct Tables {
+    const float2 *tw_x;      // exp(-2 pi i m / M), m < M
+    const float2 *tw_post;   // exp(-2 pi i k / nx), k < M  (real-FFT split twiddles)
+    const float2 *tw_y;      // exp(-2 pi i m / ny)
+    const float2 *tw_z;      // exp(-2 pi i m / nz)
+    const float *kx;         // [M + 1]  (index M is the Nyquist wavenumber -pi/dx)
+    const float *ky;         // [ny]
+    const float *kz;         // [nz]
+    const float2 *dpx, *dmx; // [M + 1]  i kx exp(+- i kx dx / 2)
+    const float2 *dpy, *dmy; // [ny]
+    const float2 *dpz, *dmz; // [nz]
+    const float *pml_x, *pml_sx;   // [nx] regular / staggered PML factors
+    const float *pml_y, *pml_sy;   // [ny]
+    const float *pml_z, *pml_sz;   // [nz]
+};
+
+struct SourceDev {
+    int n_elements;
+    const int *row_ptr;      // [rows + 1] CSR over grid rows (null -> no source)
+    const int *xpos;         // x of each source point
+    const int *elem;         // element of each point
+    const float *coef;       // 2 dt / (3 c0 dx) at each point
+    const double *amp_cos;   // a_e cos(phi_e)
+    const double *amp_sin;   // a_e sin(phi_e)
+    const float *signal;     // optional [n_elements * n_samples]
+    int n_samples;
+    double omega_dt;         // 2 pi f dt
+    float *drive;            // [n_elements] value of s_e at the current half step
+};
+
+struct SensorDev {
+    int all_points;          // 1 -> one accumulator per grid point
+    int n_points;
+    const int *row_ptr;      // [rows + 1] CSR (mask mode)
+    const int *xpos;
+    const int *sid;          // sensor id (position in the sorted index list)
+    float *p_max;            // null when not recorded
+    float *p_sum2;           // null when neither p_rms nor intensity is recorded
+    float *series;           // [capacity * n_points] or null
+    int capacity;
+    int record_start;
+};
+
+struct Medium {
+    Coef dtr[3];             // dt / rho0 at the staggered points of u_x, u_y, u_z
+    Coef rho0;               // rho0
+    Coef c0sq;               // c0^2
+    Coef nl;                 // c0^2 B/A / (2 rho0)            (nonlinear)
+    Coef ta;                 // c0^2 tau                        (absorbing)
+    Coef tb;                 // -c0^2 eta                       (absorbing)
+    int nonlinear;
+    int absorbing;
+};
+
+struct Counters {
+    int *step;               // steps taken (device)
+    int *nonfinite;          // first step with a non-finite pressure (INT_MAX if none)
+};
+
+// kernel launch records -------------------------------------------------------
+enum KernelClass {
+    KC_YFWD = 0, KC_YINV, KC_ZGRAD, KC_ZDIV, KC_ZABS, KC_ZPAIR,
+    KC_XVEL, KC_XDEN, KC_XEOS, KC_XAUX, KC_COUNT
+};
+
+struct StepBuffers {
+    float *u[3];
+    float *rho[3];
+    float *rho_total;        // sum of the split densities (absorbing only)
+    float2 *S[7];            // packed half-spectrum scratch arrays
+};
+
+struct LaunchCfg {
+    FftPlan px, pxi;         // x forward plan (length M) and its reverse
+    FftPlan py, pyi;         // y
+    FftPlan pz, pzi;         // z
+    int tb_x;                // rows per block in x kernels
+    int tb_y;                // columns per block in y kernels
+    int tb_z;                // columns per block in z kernels
+};
+
+// launchers (kernels.hip) -----------------------------------------------------
+hipError_t launch_ypass(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
+                        float2 *const *fields, int nfields, bool inverse,
+                        const Counters *prologue, const SourceDev *src);
+hipError_t launch_zfused(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
+                         int mode, float2 *const *in, float2 *const *out, int which);
+hipError_t launch_zpair(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
+                        int mode, float2 *const *in, float2 *const *out);
+hipError_t launch_xvel(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
+                       const Medium &m, float2 *const *S, float *const *u);
+hipError_t launch_xden(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
+                       const Medium &m, const SourceDev &src, const SensorDev &sen,
+                       const Counters &cnt, float2 *const *Sin, float *const *rho,
+                       float *rho_total, float2 *const *Sout);
+hipError_t launch_xeos(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
+                       const Medium &m, const SensorDev &sen, const Counters &cnt,
+                       float2 *const *Sin, const float *rho_total, float2 *Sout);
+// real field -> packed x-spectrum (forward) or back, scaled by `scale`
+hipError_t launch_xfwd(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
+                       const float *src, float2 *dst);
+hipError_t launch_xinv(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
+                       const float2 *src, float *dst, float scale);
+hipError_t launch_fill(hipStream_t s, float *p, size_t n, float v);
+hipError_t launch_fill_int(hipStream_t s, int *p, size_t n, int v);
+// dst[i] = f(sum2[i]) for the gather of p_rms / intensity
+hipError_t launch_finalize(hipStream_t s, const float *sum2, float *dst, size_t n, float inv_count,
+                           int mode, Coef rho0, Coef c0sq, const int *index);
+
+}  // namespace kw

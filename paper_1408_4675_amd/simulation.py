@@ -1,0 +1,188 @@
+"""Python front end of the HIP solver: PyTorch supplies the device workspace
+and the stream, libkw.so does all the work.
+
+    sim = Simulation(scenario)           # kw_create
+    sim.step(200)                        # kw_step (asynchronous)
+    p_max = sim.gather(REC_P_MAX)        # kw_gather -> torch tensor on the GPU
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _abi as A
+from .scenarios import Scenario
+
+_P = C.POINTER
+
+
+def _fptr(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    return a.ctypes.data_as(_P(C.c_float))
+
+
+def _map_or_scalar(v, n):
+    """(pointer-keeper array or None, scalar)"""
+    if np.isscalar(v) or np.ndim(v) == 0:
+        return None, float(v)
+    a = np.ascontiguousarray(np.asarray(v, np.float32).reshape(-1))
+    if a.size != n:
+        raise ValueError("medium map has %d values, grid has %d" % (a.size, n))
+    return a, 0.0
+
+
+class _Marshalled:
+    """ctypes structs for one scenario; keeps the numpy buffers alive."""
+
+    def __init__(self, sc: Scenario):
+        g, m = sc.grid, sc.medium
+        n = g.nx * g.ny * g.nz
+        self.keep = []
+        self.grid = A.KwGrid(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.dt, g.cfl,
+                             (C.c_int32 * 3)(*g.pml_size), (C.c_double * 3)(*g.pml_alpha))
+        fields = {}
+        for name in ("c0", "rho0", "alpha0", "bona"):
+            arr, sc_val = _map_or_scalar(getattr(m, name), n)
+            self.keep.append(arr)
+            fields[name] = (_fptr(arr), sc_val)
+        flags = (A.KW_NONLINEAR if m.nonlinear else 0) | (A.KW_ABSORBING if m.absorbing else 0)
+        self.medium = A.KwMedium(fields["c0"][0], fields["c0"][1], fields["rho0"][0],
+                                 fields["rho0"][1], fields["alpha0"][0], fields["alpha0"][1],
+                                 fields["bona"][0], fields["bona"][1], m.alpha_power, m.c_ref,
+                                 flags)
+        s = sc.source
+        if s is not None and len(s.index) > 0:
+            idx = np.ascontiguousarray(s.index, np.int64)
+            elem = None if s.element is None else np.ascontiguousarray(s.element, np.int32)
+            amp = np.ascontiguousarray(s.amp, np.float32)
+            ph = np.ascontiguousarray(s.phase, np.float32)
+            sig = None if s.signal is None else np.ascontiguousarray(s.signal, np.float32)
+            self.keep += [idx, elem, amp, ph, sig]
+            self.source = A.KwSource(idx.size, idx.ctypes.data_as(_P(C.c_int64)),
+                                     None if elem is None else elem.ctypes.data_as(_P(C.c_int32)),
+                                     amp.size, _fptr(amp), _fptr(ph), s.freq, _fptr(sig),
+                                     0 if sig is None else sig.shape[1])
+        else:
+            self.source = A.KwSource()
+        z = sc.sensor
+        if z.index is not None:
+            sidx = np.ascontiguousarray(z.index, np.int64)
+            self.keep.append(sidx)
+            self.sensor = A.KwSensor(z.record, sidx.size, sidx.ctypes.data_as(_P(C.c_int64)),
+                                     z.record_start, z.series_capacity)
+        else:
+            self.sensor = A.KwSensor(z.record, 0, None, z.record_start, z.series_capacity)
+
+    def args(self):
+        return (C.byref(self.grid), C.byref(self.medium), C.byref(self.source),
+                C.byref(self.sensor))
+
+
+def workspace_size(sc: Scenario) -> int:
+    lib = A.load()
+    m = _Marshalled(sc)
+    n = lib.kw_workspace_size(*m.args())
+    if n == 0:
+        raise A.KwError(A.KW_EINVAL, lib.kw_last_error().decode())
+    return int(n)
+
+
+class Simulation:
+    def __init__(self, sc: Scenario, device: str = "cuda", stream: Optional[torch.cuda.Stream] = None,
+                 graph_steps: Optional[int] = None):
+        self.lib = A.load()
+        self.scenario = sc
+        self.device = torch.device(device)
+        m = _Marshalled(sc)
+        nbytes = self.lib.kw_workspace_size(*m.args())
+        if nbytes == 0:
+            raise A.KwError(A.KW_EINVAL, self.lib.kw_last_error().decode())
+        self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        # the workspace is allocated on the current stream; order it before the sim's stream
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        # keep the caching allocator from reusing the workspace while the
+        # simulation's stream may still use it
+        self.workspace.record_stream(self.stream)
+        handle = C.c_void_p()
+        A.check(self.lib.kw_create(*m.args(), C.c_void_p(self.workspace.data_ptr()),
+                                   C.c_size_t(nbytes), C.c_void_p(self.stream.cuda_stream),
+                                   C.byref(handle)))
+        self.handle = handle
+        self.npts = sc.grid.npts
+        if graph_steps is not None:
+            A.check(self.lib.kw_set_graph(self.handle, int(graph_steps)))
+
+    # ------------------------------------------------------------------
+    def step(self, n: int = 1):
+        A.check(self.lib.kw_step(self.handle, int(n)))
+
+    def gather(self, what: int, device: bool = True):
+        nb = self.lib.kw_gather_bytes(self.handle, what)
+        if nb < 0:
+            raise A.KwError(A.KW_EINVAL, "unknown gather target")
+        n = max(nb // 4, 1)
+        if device:
+            out = torch.empty(n, dtype=torch.float32, device=self.device)
+            ptr, isdev = out.data_ptr(), 1
+        else:
+            out = np.empty(n, np.float32)
+            ptr, isdev = out.ctypes.data, 0
+        A.check(self.lib.kw_gather(self.handle, what, C.c_void_p(ptr), C.c_size_t(n * 4), isdev))
+        return out[: nb // 4]
+
+    def set_field(self, field: int, values):
+        if isinstance(values, torch.Tensor):
+            v = values.detach().to(self.device, torch.float32).contiguous().reshape(-1)
+            torch.cuda.current_stream(self.device).synchronize()
+            A.check(self.lib.kw_set_field(self.handle, field, C.c_void_p(v.data_ptr()), 1))
+        else:
+            v = np.ascontiguousarray(np.asarray(values, np.float32).reshape(-1))
+            if v.size != self.npts:
+                raise ValueError("field has %d values, grid has %d" % (v.size, self.npts))
+            A.check(self.lib.kw_set_field(self.handle, field, C.c_void_p(v.ctypes.data), 0))
+
+    def get_field(self, field: int) -> np.ndarray:
+        out = np.empty(self.npts, np.float32)
+        A.check(self.lib.kw_gather_field(self.handle, field, C.c_void_p(out.ctypes.data), 0))
+        return out
+
+    def profile(self, on: bool):
+        A.check(self.lib.kw_profile(self.handle, 1 if on else 0))
+
+    def set_plan(self, axis: int, radices, tile: int = 0):
+        arr = (C.c_int32 * len(radices))(*radices) if radices else None
+        A.check(self.lib.kw_set_plan(self.handle, axis, arr, len(radices) if radices else 0, tile))
+
+    def stats(self) -> dict:
+        st = A.KwStats()
+        A.check(self.lib.kw_stats(self.handle, C.byref(st)))
+        classes = {}
+        for i in range(st.n_classes):
+            name = st.class_name[i].value.decode()
+            classes[name] = dict(ms=st.class_ms[i], launches=st.class_launches[i],
+                                 bytes=st.class_bytes[i])
+        return dict(steps=st.steps, nonfinite_step=st.nonfinite_step, dt=st.dt, c_ref=st.c_ref,
+                    workspace_bytes=st.workspace_bytes,
+                    fft_forward_per_step=st.fft_forward_per_step,
+                    fft_inverse_per_step=st.fft_inverse_per_step,
+                    kernels_per_step=st.kernels_per_step, classes=classes)
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.stream.synchronize()
+            self.lib.kw_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
