@@ -1,0 +1,197 @@
+"""Throughput of the k-space pseudospectral time step on one MI355X.
+
+Workload (the headline configuration): 256^3 layered heterogeneous tissue,
+nonlinear and absorbing, 1 MHz focused bowl at 5 MPa, 20-point PML, p_max and
+p_rms recorded at every grid point, float32.  A second line item times the
+1024^3 homogeneous water grid (3 MHz bowl, one focal sensor).
+
+Prints one JSON line.  `value` = grid-point updates per second at 256^3 with
+every input resident in HBM.  The timed region runs with per-kernel HIP
+events on the simulation's stream, from which the roofline of the dominant
+kernel class is computed (algorithmic bytes per launch / average duration).
+The CPU baseline times the FP64 oracle on a bounded sample of the same 256^3
+workload on the host cores.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "fft_dev.h", "kw_internal.h"):
+        with open(os.path.join(ROOT, "paper_1408_4675_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_class, launches_bytes):
+    """HBM bytes per launch of `kernel_class` from the committed rocprofv3 PMC
+    summary, if it was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    k = d.get("kernels", {}).get(kernel_class)
+    return None if k is None else k.get("hbm_bytes_per_launch")
+
+
+def time_workload(scen, steps, warmup, profile=True):
+    import torch
+    from paper_1408_4675_amd.simulation import Simulation
+    sim = Simulation(scen)
+    sim.step(warmup)
+    sim.synchronize()
+    if profile:
+        sim.stats()                 # resolve anything pending
+        sim.profile(True)
+        base = sim.stats()["classes"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.synchronize()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stats = sim.stats()
+    if profile:
+        sim.profile(False)
+        for k, v in stats["classes"].items():
+            v["ms"] -= base[k]["ms"]
+            v["launches"] -= base[k]["launches"]
+    # nonfinite check (also proves the run produced finite pressures)
+    if stats["nonfinite_step"] >= 0:
+        raise RuntimeError("non-finite pressure at step %d" % stats["nonfinite_step"])
+    sim.close()
+    return (t1 - t0), stats
+
+
+def roofline(stats, npts):
+    classes = {k: v for k, v in stats["classes"].items() if v["launches"] > 0}
+    dom = max(classes, key=lambda k: classes[k]["ms"])
+    c = classes[dom]
+    avg_s = c["ms"] / c["launches"] / 1e3
+    achieved = c["bytes"] / avg_s / 1e9
+    per_class = {k: dict(ms_per_launch=round(v["ms"] / v["launches"], 5),
+                         launches=v["launches"],
+                         algorithmic_bytes=v["bytes"],
+                         gbs=round(v["bytes"] / (v["ms"] / v["launches"] / 1e3) / 1e9, 1)
+                         if v["bytes"] > 0 else None)
+                 for k, v in classes.items()}
+    return dom, dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                     frac=round(achieved / HBM_PEAK_GBS, 4),
+                     traffic=measured_traffic(dom, c["bytes"]),
+                     kernel=dom, algorithmic_bytes_per_launch=c["bytes"],
+                     avg_launch_ms=round(avg_s * 1e3, 5)), per_class
+
+
+def pass_model_bytes(stats):
+    """Algorithmic bytes of one step: sum over kernels of bytes x launches."""
+    tot_b, steps = 0.0, None
+    for k, v in stats["classes"].items():
+        tot_b += v["bytes"] * v["launches"]
+    return tot_b
+
+
+def cpu_baseline(scen, warm=1, steps=2):
+    import numpy as np
+    from oracle import Oracle
+    o = Oracle(scen)
+    o.step(warm)
+    t0 = time.perf_counter()
+    o.step(steps)
+    dt = time.perf_counter() - t0
+    return dict(value=round(scen.grid.npts * steps / dt, 1), unit="grid-point updates/s",
+                cores=o.workers, kind="oracle",
+                sample="FP64 NumPy/SciPy oracle, %d timed steps (after %d warm-up) of the same "
+                       "256^3 tissue workload; %.1f s" % (steps, warm, dt))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-large", action="store_true", help="skip the 1024^3 item")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--large-steps", type=int, default=100)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1408_4675_amd import scenarios as sc
+    from paper_1408_4675_amd import _abi
+    _abi.load()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+    log("building 256^3 tissue workload")
+    scen = sc.tissue_bowl(seed=0, n=256, steps=args.steps)
+    npts = scen.grid.npts
+    log("timing %d steps after %d warm-up" % (args.steps, args.warmup))
+    secs, stats = time_workload(scen, args.steps, args.warmup)
+    ms_per_step = secs / args.steps * 1e3
+    value = npts * args.steps / secs
+    dom, roof, per_class = roofline(stats, npts)
+    step_bytes = pass_model_bytes(stats) / args.steps
+    out = dict(
+        metric="grid-point updates/s (256^3 heterogeneous nonlinear absorbing step, FP32)",
+        value=round(value, 1), unit="grid-point updates/s", n_gpus=1, steps=args.steps,
+        warmup=args.warmup, ms_per_step=round(ms_per_step, 4), higher_is_better=True,
+        scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
+        config=dict(workload="tissue_bowl_256: 256^3 layered tissue + inclusions (seed 0), "
+                             "1 MHz 5 MPa bowl R15/aperture 18 mm, PML 20, CFL 0.3, "
+                             "p_max+p_rms at all points", grid=[256, 256, 256],
+                    kernels_per_step=stats["kernels_per_step"],
+                    fft_per_step=stats["fft_forward_per_step"] + stats["fft_inverse_per_step"]),
+        roofline=roof,
+        step_roofline=dict(pass_model_bytes_per_point=round(step_bytes / npts, 2),
+                           achieved_gbs=round(step_bytes / (ms_per_step / 1e3) / 1e9, 1),
+                           frac=round(step_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4)),
+        per_class=per_class,
+    )
+    if not args.no_large:
+        try:
+            log("building 1024^3 water workload")
+            big = sc.water_bowl_large(n=1024, steps=args.large_steps)
+            log("timing 1024^3: %d steps after 5 warm-up" % args.large_steps)
+            bsecs, bstats = time_workload(big, args.large_steps, 5)
+            bms = bsecs / args.large_steps * 1e3
+            bdom, broof, bper = roofline(bstats, big.grid.npts)
+            bstep = pass_model_bytes(bstats) / args.large_steps
+            out["large"] = dict(workload="water_bowl_1024: 1024^3 homogeneous water, 3 MHz 2 MPa "
+                                         "bowl, PML 20, one focal sensor",
+                                value=round(big.grid.npts * args.large_steps / bsecs, 1),
+                                unit="grid-point updates/s", ms_per_step=round(bms, 3),
+                                steps=args.large_steps, roofline=broof,
+                                step_roofline=dict(
+                                    pass_model_bytes_per_point=round(bstep / big.grid.npts, 2),
+                                    achieved_gbs=round(bstep / (bms / 1e3) / 1e9, 1),
+                                    frac=round(bstep / (bms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)),
+                                per_class=bper)
+        except Exception as e:   # report, but keep the headline line
+            out["large"] = dict(error=str(e))
+    if not args.no_cpu:
+        log("timing the CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline(sc.tissue_bowl(seed=0, n=256, steps=3))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
