@@ -35,17 +35,34 @@ def _run(cmd):
     return r.stdout
 
 
-def build(verbose: bool = False) -> str:
+HIP_SOURCES = ("kernels_yz.hip", "kernels_x.hip", "kernels_util.hip")
+
+
+def build(verbose: bool = False, extra_flags=()) -> str:
+    """Compile every HIP translation unit for gfx950 (in parallel) and link
+    libkw.so next to this file."""
     hipcc = _hipcc()
     with tempfile.TemporaryDirectory(prefix="kwbuild_") as tmp:
-        k_obj = os.path.join(tmp, "kernels.o")
+        jobs = []
+        objs = []
+        for src in HIP_SOURCES:
+            obj = os.path.join(tmp, src + ".o")
+            objs.append(obj)
+            cmd = ([hipcc, "-x", "hip", "--offload-arch=" + ARCH] + COMMON + DEVICE_FLAGS
+                   + list(extra_flags) + ["-c", os.path.join(CSRC, src), "-o", obj])
+            jobs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE,
+                                               stderr=subprocess.STDOUT, text=True)))
         e_obj = os.path.join(tmp, "engine.o")
-        out = _run([hipcc, "-x", "hip", "--offload-arch=" + ARCH] + COMMON + DEVICE_FLAGS
-                   + ["-c", os.path.join(CSRC, "kernels.hip"), "-o", k_obj])
-        out += _run([hipcc] + COMMON + ["-c", os.path.join(CSRC, "engine.cpp"), "-o", e_obj])
+        objs.append(e_obj)
+        out = _run([hipcc] + COMMON + ["-c", os.path.join(CSRC, "engine.cpp"), "-o", e_obj])
+        for cmd, pr in jobs:
+            o, _ = pr.communicate()
+            out += o
+            if pr.returncode != 0:
+                sys.stderr.write(o)
+                raise RuntimeError("command failed: " + " ".join(cmd))
         tmp_lib = LIB + ".tmp"
-        out += _run([hipcc, "--offload-arch=" + ARCH, "-shared", "-fPIC", k_obj, e_obj,
-                     "-o", tmp_lib])
+        out += _run([hipcc, "--offload-arch=" + ARCH, "-shared", "-fPIC"] + objs + ["-o", tmp_lib])
         os.replace(tmp_lib, LIB)
     if verbose and out.strip():
         print(out)

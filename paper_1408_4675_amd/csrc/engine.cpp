@@ -97,6 +97,7 @@ bool plan_from_radices(int n, const std::vector<int> &rad, FftPlan &p) {
         for (int q : kRadices32) okr |= (q == r);
         if (!okr) return false;
         p.radix[i] = r;
+        p.code |= (unsigned long long)r << (6 * i);
         prod *= r;
         p.L = std::max(p.L, n / r);
         p.rmax = std::max(p.rmax, r);
@@ -104,10 +105,8 @@ bool plan_from_radices(int n, const std::vector<int> &rad, FftPlan &p) {
     return prod == n;
 }
 
-bool default_plan(int n, FftPlan &p) {
-    if (n == 1) {
-        return false;
-    }
+bool generic_plan(int n, FftPlan &p) {
+    if (n < 2) return false;
     std::vector<int> cur, best;
     int best_np = INT_MAX, best_min = 0;
     search(n, 16, cur, best, best_np, best_min);
@@ -127,8 +126,75 @@ bool default_plan(int n, FftPlan &p) {
 
 FftPlan reversed(const FftPlan &p) {
     FftPlan q = p;
-    for (int i = 0; i < p.np; ++i) q.radix[i] = p.radix[p.np - 1 - i];
+    q.code = 0;
+    for (int i = 0; i < p.np; ++i) {
+        q.radix[i] = p.radix[p.np - 1 - i];
+        q.code |= (unsigned long long)q.radix[i] << (6 * i);
+    }
     return q;
+}
+
+bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+// Default elements per thread of the fixed-width engine for a power-of-two
+// length: 16 for the column passes, 8 for the x rows (whose fused updates keep
+// more values live); short transforms use 8.
+int fixed_width(int n, int axis) { return (axis > 0 && n >= 64) ? 16 : 8; }
+
+bool fixed_plan_from_radices(int n, int E, const std::vector<int> &rad, FftPlan &p) {
+    if (rad.empty() || (int)rad.size() > kMaxPasses) return false;
+    long prod = 1;
+    p = FftPlan{};
+    p.n = n;
+    p.np = (int)rad.size();
+    p.L = n / E;
+    p.rmax = 0;
+    for (int i = 0; i < p.np; ++i) {
+        const int r = rad[i];
+        if (!(r == 2 || r == 4 || r == 8 || r == 16) || r > E || E % r) return false;
+        p.radix[i] = r;
+        p.code |= (unsigned long long)r << (6 * i);
+        prod *= r;
+        p.rmax = std::max(p.rmax, r);
+    }
+    return prod == n && n % E == 0;
+}
+
+// Choose the engine and plans of one axis of transform length n.  `rad`, when
+// given, is a caller-chosen radix schedule (the autotuner's).
+bool axis_plan(int n, int axis, const std::vector<int> *rad, int &eng, FftPlan &f, FftPlan &i) {
+    if (is_pow2(n) && n >= 16) {
+        int E = fixed_width(n, axis);
+        std::vector<int> r;
+        if (rad) {
+            r = *rad;
+            // the width is the largest radix of a caller-chosen schedule
+            E = *std::max_element(r.begin(), r.end()) > 8 ? 16 : 8;
+        } else {
+            int m = n;
+            while (m > 1) {
+                int q = E;
+                while (m % q) q /= 2;
+                r.push_back(q);
+                m /= q;
+            }
+        }
+        if (fixed_plan_from_radices(n, E, r, f)) {
+            eng = E == 16 ? ENG_F16 : ENG_F8;
+            i = f;
+            return true;
+        }
+        if (!rad) return false;
+        // a caller schedule outside the fixed engine's radices runs on the generic one
+    }
+    if (rad) {
+        if (!plan_from_radices(n, *rad, f)) return false;
+    } else if (!generic_plan(n, f)) {
+        return false;
+    }
+    eng = f.rmax > 16 ? ENG_G32 : ENG_G16;
+    i = reversed(f);
+    return true;
 }
 
 // ---------------------------------------------------------------------------
@@ -390,7 +456,7 @@ namespace {
 
 const char *kClassNames[KC_COUNT] = {"ypass_fwd", "ypass_inv", "zfused_grad", "zfused_div",
                                      "zfused_abs", "zpair",     "xvel",        "xden",
-                                     "xeos",      "xaux"};
+                                     "xeos"};
 
 hipEvent_t take_event(kw_sim *s) {
     if (!s->pool.empty()) {
@@ -464,13 +530,13 @@ hipError_t enqueue_step(kw_sim *s) {
     float2 *s123[3] = {S[1], S[2], S[3]};
     float2 *s456[3] = {S[4], S[5], S[6]};
     KW_L(KC_YFWD, 2, launch_ypass(st, g, c, t, s0, 1, false, &s->counters, &s->src));
-    KW_L(KC_ZGRAD, 4, launch_zfused(st, g, c, t, 0, s0, s123, 0));
+    KW_L(KC_ZGRAD, 4, launch_zfused(st, g, c, t, 0, s0, s123));
     KW_L(KC_ZPAIR, 0, launch_zpair(st, g, c, t, 0, s0, s123));
     KW_L(KC_YINV, 6, launch_ypass(st, g, c, t, s123, 3, true, nullptr, nullptr));
     KW_L(KC_XVEL, 12 + (ms.het[MED_DTRX] ? 3 : 0),
          launch_xvel(st, g, c, t, s->med, s123, s->buf.u));
     KW_L(KC_YFWD, 6, launch_ypass(st, g, c, t, s123, 3, false, nullptr, nullptr));
-    KW_L(KC_ZDIV, 6, launch_zfused(st, g, c, t, 1, s123, s456, 0));
+    KW_L(KC_ZDIV, 6, launch_zfused(st, g, c, t, 1, s123, s456));
     KW_L(KC_ZPAIR, 0, launch_zpair(st, g, c, t, 1, s123, s456));
     KW_L(KC_YINV, 6, launch_ypass(st, g, c, t, s456, 3, true, nullptr, nullptr));
     if (absorbing) {
@@ -481,9 +547,9 @@ hipError_t enqueue_step(kw_sim *s) {
         float2 *s12[2] = {S[1], S[2]};
         float2 *s45[2] = {S[4], S[5]};
         KW_L(KC_YFWD, 4, launch_ypass(st, g, c, t, s12, 2, false, nullptr, nullptr));
-        KW_L(KC_ZABS, 4, launch_zfused(st, g, c, t, 2, s12, s45, 0));
+        KW_L(KC_ZABS, 4, launch_zfused(st, g, c, t, 2, s12, s45));
         KW_L(KC_ZPAIR, 0, launch_zpair(st, g, c, t, 2, s12, s45));
-        KW_L(KC_YINV, 4, launch_ypass(st, g, c, t, s45, 2, true, nullptr, nullptr));
+            KW_L(KC_YINV, 4, launch_ypass(st, g, c, t, s45, 2, true, nullptr, nullptr));
         const double med_units = (ms.het[MED_C0SQ] ? 1 : 0) + (ms.het[MED_NL] ? 1 : 0) +
                                  (ms.het[MED_TA] ? 2 : 0);
         KW_L(KC_XEOS, 4 + med_units + sens_units,
@@ -554,6 +620,8 @@ int pick_tiles(kw_sim *s, int tile_y, int tile_z) {
     };
     c.tb_y = col_tile(g.ny, c.py.L, tile_y);
     c.tb_z = col_tile(g.nz, c.pz.L, tile_z);
+    if (c.tb_z < 2 || (c.tb_z & 1))
+        return fail(KW_EUNSUPPORTED, "z column tile must be even and >= 2 (got %d)", c.tb_z);
     const size_t xl = (size_t)c.tb_x * (g.M + (g.M >> 4) + 1) * sizeof(float2) +
                       (size_t)c.tb_x * g.nx * sizeof(float);
     int rc;
@@ -562,7 +630,6 @@ int pick_tiles(kw_sim *s, int tile_y, int tile_z) {
         return rc;
     if ((rc = check_tb("z pass", c.tb_z, c.pz.L, (size_t)c.tb_z * g.nz * sizeof(float2))) != KW_OK)
         return rc;
-    if (2 * c.pz.L > 512) return fail(KW_EUNSUPPORTED, "z pair pass too large");
     return KW_OK;
 }
 
@@ -604,11 +671,10 @@ int kw_create(const kw_grid *grid, const kw_medium *medium, const kw_source *sou
 
     // FFT plans (host only, may fail before any device work)
     LaunchCfg cfg{};
-    if (!default_plan(M, cfg.px) || !default_plan(ny, cfg.py) || !default_plan(nz, cfg.pz))
+    if (!axis_plan(M, 0, nullptr, cfg.eng_x, cfg.px, cfg.pxi) ||
+        !axis_plan(ny, 1, nullptr, cfg.eng_y, cfg.py, cfg.pyi) ||
+        !axis_plan(nz, 2, nullptr, cfg.eng_z, cfg.pz, cfg.pzi))
         return fail(KW_EUNSUPPORTED, "no FFT schedule for %d x %d x %d", nx, ny, nz);
-    cfg.pxi = reversed(cfg.px);
-    cfg.pyi = reversed(cfg.py);
-    cfg.pzi = reversed(cfg.pz);
 
     // medium scalars / statistics in float64
     auto val = [](const float *a, double sc, size_t i) { return a ? (double)a[i] : sc; };
@@ -1125,13 +1191,13 @@ int kw_set_plan(kw_sim *s, int axis, const int32_t *radices, int32_t n_radices, 
     const int n = axis == 0 ? s->g.M : axis == 1 ? s->g.ny : s->g.nz;
     if (radices && n_radices > 0) {
         std::vector<int> rad(radices, radices + n_radices);
-        FftPlan p;
-        if (!plan_from_radices(n, rad, p))
+        FftPlan f, r;
+        int eng;
+        if (!axis_plan(n, axis, &rad, eng, f, r))
             return fail(KW_EINVAL, "radices do not form a schedule for length %d", n);
-        FftPlan &f = axis == 0 ? s->cfg.px : axis == 1 ? s->cfg.py : s->cfg.pz;
-        FftPlan &r = axis == 0 ? s->cfg.pxi : axis == 1 ? s->cfg.pyi : s->cfg.pzi;
-        f = p;
-        r = reversed(p);
+        (axis == 0 ? s->cfg.px : axis == 1 ? s->cfg.py : s->cfg.pz) = f;
+        (axis == 0 ? s->cfg.pxi : axis == 1 ? s->cfg.pyi : s->cfg.pzi) = r;
+        (axis == 0 ? s->cfg.eng_x : axis == 1 ? s->cfg.eng_y : s->cfg.eng_z) = eng;
     }
     int rc = pick_tiles(s, axis == 1 ? tile : s->cfg.tb_y, axis == 2 ? tile : s->cfg.tb_z);
     if (rc == KW_OK && axis == 0 && tile > 0) {

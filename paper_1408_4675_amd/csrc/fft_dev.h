@@ -271,7 +271,7 @@ __device__ __forceinline__ void fft_run(const FftPlan &P, const float2 *__restri
                                         const Lds &lds, float2 (&v)[RM]) {
     int Ns = 1;
     for (int p = 0; p < P.np; ++p) {
-        const int R = P.radix[p];
+        const int R = plan_radix(P, p);
         const int nb = P.n / R;
         const bool act = t < nb;
         if (p > 0) {
@@ -307,5 +307,123 @@ __device__ __forceinline__ void fft_run(const FftPlan &P, const float2 *__restri
     }
     __syncthreads();
 }
+
+
+// --- fixed-width engine for power-of-two lengths -------------------------------
+// Every thread owns E elements: x[t + m L], m < E, with L = n / E threads per
+// transform, in the first pass and after the last pass whatever the radix
+// schedule (every radix divides E).  A pass of radix R runs E/R butterflies per
+// thread, j = t + b L (b < E/R); butterfly j reads x[j + r n/R], which is
+// element t + L (b + r E/R) -- register b + r E/R.
+template <int E, int R, bool INV, int Bi>
+struct FixedBfly {
+    template <class Lds>
+    __device__ __forceinline__ static void run(float2 (&v)[E], int t, int L, int Ns, int st,
+                                               const float2 *__restrict__ tw, const Lds &lds,
+                                               bool write) {
+        constexpr int B = E / R;
+        if constexpr (Bi < B) {
+            const int j = t + Bi * L;
+            const int k = j & (Ns - 1);
+            if (Ns > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    const float2 w = tw[k * r * st];
+                    v[Bi + r * B] = INV ? c_mulc(v[Bi + r * B], w) : c_mul(v[Bi + r * B], w);
+                }
+            }
+            Dft<R, INV>::template run<B, Bi>(v);
+            if (write) {
+                const int base = (j - k) * R + k;
+#pragma unroll
+                for (int r = 0; r < R; ++r) lds.st(base + r * Ns, v[Bi + r * B]);
+            }
+            FixedBfly<E, R, INV, Bi + 1>::run(v, t, L, Ns, st, tw, lds, write);
+        }
+    }
+};
+
+template <int E, int R, bool INV, class Lds>
+__device__ __forceinline__ void pass_fixed(float2 (&v)[E], int t, int L, int Ns, int st,
+                                           const float2 *__restrict__ tw, const Lds &lds,
+                                           bool write) {
+    FixedBfly<E, R, INV, 0>::run(v, t, L, Ns, st, tw, lds, write);
+}
+
+// On entry v[m] = x[t + m L]; on exit v[m] = X[t + m L] (m < E, t < L).
+template <bool INV, int E, class Lds>
+__device__ __forceinline__ void fft_fixed(const FftPlan &P, const float2 *__restrict__ tw, int t,
+                                          const Lds &lds, float2 (&v)[E]) {
+    const int L = P.L;
+    int Ns = 1;
+    for (int p = 0; p < P.np; ++p) {
+        const int R = plan_radix(P, p);
+        if (p > 0) {
+            __syncthreads();
+#pragma unroll
+            for (int m = 0; m < E; ++m) v[m] = lds.ld(t + m * L);
+            __syncthreads();
+        }
+        const int st = P.n / (Ns * R);
+        const bool write = p < P.np - 1;
+        switch (R) {
+        case 2: pass_fixed<E, 2, INV>(v, t, L, Ns, st, tw, lds, write); break;
+        case 4: pass_fixed<E, 4, INV>(v, t, L, Ns, st, tw, lds, write); break;
+        case 8: pass_fixed<E, 8, INV>(v, t, L, Ns, st, tw, lds, write); break;
+        default:
+            if constexpr (E >= 16) pass_fixed<E, 16, INV>(v, t, L, Ns, st, tw, lds, write);
+            break;
+        }
+        Ns *= R;
+    }
+    __syncthreads();
+}
+
+// Engine policies used by the kernels.  `in_*` is the register layout of the
+// input of the plan being run and `out_*` the layout of its output.  For the
+// generic engine the inverse of an axis runs the reversed plan, so the output
+// layout of a forward transform is the input layout of the inverse one and
+// vice versa; for the fixed engine both layouts are t + m L for every plan.
+template <int RM>
+struct EngGeneric {
+    static constexpr int E = RM;
+    __device__ static __forceinline__ int in_count(const FftPlan &P, int t) {
+        const int R = plan_radix(P, 0);
+        return t < P.n / R ? R : 0;
+    }
+    __device__ static __forceinline__ int in_index(const FftPlan &P, int t, int m) {
+        return t + m * (P.n / plan_radix(P, 0));
+    }
+    __device__ static __forceinline__ int out_count(const FftPlan &P, int t) {
+        const int R = plan_radix(P, P.np - 1);
+        return t < P.n / R ? R : 0;
+    }
+    __device__ static __forceinline__ int out_index(const FftPlan &P, int t, int m) {
+        return t + m * (P.n / plan_radix(P, P.np - 1));
+    }
+    template <bool INV, class Lds>
+    __device__ static __forceinline__ void run(const FftPlan &P, const float2 *tw, int t,
+                                               const Lds &lds, float2 (&v)[RM]) {
+        fft_run<INV, RM>(P, tw, t, lds, v);
+    }
+};
+
+template <int EE>
+struct EngFixed {
+    static constexpr int E = EE;
+    __device__ static __forceinline__ int in_count(const FftPlan &, int) { return EE; }
+    __device__ static __forceinline__ int in_index(const FftPlan &P, int t, int m) {
+        return t + m * P.L;
+    }
+    __device__ static __forceinline__ int out_count(const FftPlan &, int) { return EE; }
+    __device__ static __forceinline__ int out_index(const FftPlan &P, int t, int m) {
+        return t + m * P.L;
+    }
+    template <bool INV, class Lds>
+    __device__ static __forceinline__ void run(const FftPlan &P, const float2 *tw, int t,
+                                               const Lds &lds, float2 (&v)[EE]) {
+        fft_fixed<INV, EE>(P, tw, t, lds, v);
+    }
+};
 
 }  // namespace kw

@@ -1,0 +1,95 @@
+// Launchers of the x-pass kernels (all FFT engines).
+#include "kernels_impl.h"
+
+namespace kw {
+
+static XArgs make_xargs(const GridDev &g, const LaunchCfg &c, const Tables &t) {
+    XArgs a{};
+    a.g = g;
+    a.t = t;
+    a.pf = c.px;
+    a.pi = c.pxi;
+    a.tb = c.tb_x;
+    return a;
+}
+static inline size_t x_lds(const GridDev &g, const LaunchCfg &c, bool line) {
+    size_t n = (size_t)c.tb_x * row_pitch(g.M) * sizeof(float2);
+    if (line) n += (size_t)c.tb_x * g.nx * sizeof(float);
+    return n;
+}
+#define KW_XLAUNCH(KERNEL, LINE)                                                     \
+    do {                                                                             \
+        dim3 grid((g.rows + c.tb_x - 1) / c.tb_x);                                   \
+        dim3 block(c.tb_x * c.px.L);                                                 \
+        size_t lds = x_lds(g, c, LINE);                                              \
+        KW_ENGINE_SWITCH(c.eng_x, hipLaunchKernelGGL((KERNEL<Eng>), grid, block, lds, s, a)); \
+    } while (0)
+
+hipError_t launch_xvel(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
+                       const Medium &m, float2 *const *S, float *const *u) {
+    XArgs a = make_xargs(g, c, t);
+    a.m = m;
+    for (int i = 0; i < 3; ++i) {
+        a.Sin[i] = S[i];
+        a.Sout[i] = S[i];
+        a.fld[i] = u[i];
+    }
+    KW_XLAUNCH(kw_xvel, false);
+    return hipGetLastError();
+}
+
+hipError_t launch_xden(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
+                       const Medium &m, const SourceDev &src, const SensorDev &sen,
+                       const Counters &cnt, float2 *const *Sin, float *const *rho,
+                       float *rho_total, float2 *const *Sout) {
+    XArgs a = make_xargs(g, c, t);
+    a.m = m;
+    a.src = src;
+    a.sen = sen;
+    a.cnt = cnt;
+    for (int i = 0; i < 3; ++i) {
+        a.Sin[i] = Sin[i];
+        a.fld[i] = rho[i];
+    }
+    a.Sout[0] = Sout[0];
+    a.Sout[1] = Sout[1];
+    a.rho_total = rho_total;
+    KW_XLAUNCH(kw_xden, true);
+    return hipGetLastError();
+}
+
+hipError_t launch_xeos(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
+                       const Medium &m, const SensorDev &sen, const Counters &cnt,
+                       float2 *const *Sin, const float *rho_total, float2 *Sout) {
+    XArgs a = make_xargs(g, c, t);
+    a.m = m;
+    a.sen = sen;
+    a.cnt = cnt;
+    a.Sin[0] = Sin[0];
+    a.Sin[1] = Sin[1];
+    a.rho_total = const_cast<float *>(rho_total);
+    a.Sout[0] = Sout;
+    KW_XLAUNCH(kw_xeos, true);
+    return hipGetLastError();
+}
+
+hipError_t launch_xfwd(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
+                       const float *src, float2 *dst) {
+    XArgs a = make_xargs(g, c, t);
+    a.rsrc = src;
+    a.Sout[0] = dst;
+    KW_XLAUNCH(kw_xfwd, false);
+    return hipGetLastError();
+}
+
+hipError_t launch_xinv(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
+                       const float2 *src, float *dst, float scale) {
+    XArgs a = make_xargs(g, c, t);
+    a.Sin[0] = src;
+    a.rdst = dst;
+    a.scale = scale;
+    KW_XLAUNCH(kw_xinv, false);
+    return hipGetLastError();
+}
+
+}  // namespace kw

@@ -1,0 +1,74 @@
+// Launchers of the y-pass and fused z-pass kernels (all FFT engines).
+#include "kernels_impl.h"
+
+namespace kw {
+
+hipError_t launch_ypass(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
+                        float2 *const *fields, int nfields, bool inverse,
+                        const Counters *prologue, const SourceDev *src) {
+    YArgs a{};
+    for (int i = 0; i < nfields; ++i) a.f[i] = fields[i];
+    a.M = g.M;
+    a.ny = g.ny;
+    a.plan = inverse ? c.pyi : c.py;
+    a.tw = t.tw_y;
+    a.tb = c.tb_y;
+    a.prologue = prologue != nullptr;
+    if (prologue) a.cnt = *prologue;
+    if (src) a.src = *src;
+    dim3 grid((g.M + a.tb - 1) / a.tb, g.nz, nfields);
+    dim3 block(a.tb * a.plan.L);
+    size_t lds = (size_t)a.tb * g.ny * sizeof(float2);
+    KW_ENGINE_SWITCH(c.eng_y, {
+        if (inverse) hipLaunchKernelGGL((kw_ypass<Eng, true>), grid, block, lds, s, a);
+        else hipLaunchKernelGGL((kw_ypass<Eng, false>), grid, block, lds, s, a);
+    });
+    return hipGetLastError();
+}
+
+static ZArgs make_zargs(const GridDev &g, const LaunchCfg &c, const Tables &t, int mode,
+                        float2 *const *in, float2 *const *out) {
+    ZArgs a{};
+    const int nin = (mode == ZM_GRAD) ? 1 : (mode == ZM_DIV) ? 3 : 2;
+    const int nout = (mode == ZM_ABS) ? 2 : 3;
+    for (int i = 0; i < nin; ++i) a.in[i] = in[i];
+    for (int i = 0; i < nout; ++i) a.out[i] = out[i];
+    a.g = g;
+    a.t = t;
+    a.pf = c.pz;
+    a.pi = c.pzi;
+    a.tb = c.tb_z;
+    a.ntiles = (g.M + a.tb - 1) / a.tb;
+    return a;
+}
+
+hipError_t launch_zfused(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
+                         int mode, float2 *const *in, float2 *const *out) {
+    const ZArgs a = make_zargs(g, c, t, mode, in, out);
+    dim3 grid(a.ntiles * g.ny);
+    dim3 block(a.tb * c.pz.L);
+    size_t lds = (size_t)a.tb * g.nz * sizeof(float2);
+    KW_ENGINE_SWITCH(c.eng_z, {
+        if (mode == ZM_GRAD) hipLaunchKernelGGL((kw_zfused<Eng, ZM_GRAD>), grid, block, lds, s, a);
+        else if (mode == ZM_DIV) hipLaunchKernelGGL((kw_zfused<Eng, ZM_DIV>), grid, block, lds, s, a);
+        else hipLaunchKernelGGL((kw_zfused<Eng, ZM_ABS>), grid, block, lds, s, a);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_zpair(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
+                        int mode, float2 *const *in, float2 *const *out) {
+    const ZArgs a = make_zargs(g, c, t, mode, in, out);
+    const int pairs_per_block = a.tb / 2;
+    dim3 grid((g.ny / 2 + 1 + pairs_per_block - 1) / pairs_per_block);
+    dim3 block(a.tb * c.pz.L);
+    size_t lds = (size_t)a.tb * g.nz * sizeof(float2);
+    KW_ENGINE_SWITCH(c.eng_z, {
+        if (mode == ZM_GRAD) hipLaunchKernelGGL((kw_zpair<Eng, ZM_GRAD>), grid, block, lds, s, a);
+        else if (mode == ZM_DIV) hipLaunchKernelGGL((kw_zpair<Eng, ZM_DIV>), grid, block, lds, s, a);
+        else hipLaunchKernelGGL((kw_zpair<Eng, ZM_ABS>), grid, block, lds, s, a);
+    });
+    return hipGetLastError();
+}
+
+}  // namespace kw

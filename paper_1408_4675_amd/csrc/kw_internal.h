@@ -1,5 +1,5 @@
 // Internal structures shared by the host engine (engine.cpp) and the HIP
-// kernels (kernels.hip).  Not part of the public ABI.
+// kernels (kernels_*.hip).  Not part of the public ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -9,18 +9,26 @@ namespace kw {
 
 constexpr int kMaxPasses = 8;
 
-// Radix schedule of one 1D transform.  Passes run in the listed order; the
-// inverse transform of an axis uses the same factors in reverse order so that
-// the last inverse pass and the first forward pass share one register layout
-// (that is what lets an inverse FFT, an element-wise update and a forward FFT
-// run back to back without an LDS exchange in between).
+// Radix schedule of one 1D transform.  Passes run in the listed order.  With
+// the generic engine the inverse transform of an axis uses the factors in
+// reverse order, so that the last inverse pass and the first forward pass
+// share one register layout; the fixed-width engine has the same layout for
+// every plan.  Either way an inverse FFT, an element-wise update and a forward
+// FFT run back to back without an LDS exchange in between.
 struct FftPlan {
     int n;                    // transform length (complex points)
     int np;                   // number of passes
-    int L;                    // threads per transform = max over passes of n / radix
+    int L;                    // threads per transform (generic: max n / radix; fixed: n / E)
     int rmax;                 // largest radix
-    int radix[kMaxPasses];
+    unsigned long long code;  // radix of pass p in bits [6p, 6p + 6): read on the device
+                              // without indexing an array (a run-time index into a
+                              // by-value kernel argument would move it to scratch)
+    int radix[kMaxPasses];    // host copy of the same schedule
 };
+
+__host__ __device__ inline int plan_radix(const FftPlan &P, int p) {
+    return (int)((P.code >> (6 * p)) & 63ull);
+}
 
 // One real field or spectrum array plus an optional per-point map: when
 // `map` is null the scalar is used everywhere.
@@ -103,7 +111,7 @@ struct Counters {
 // kernel launch records -------------------------------------------------------
 enum KernelClass {
     KC_YFWD = 0, KC_YINV, KC_ZGRAD, KC_ZDIV, KC_ZABS, KC_ZPAIR,
-    KC_XVEL, KC_XDEN, KC_XEOS, KC_XAUX, KC_COUNT
+    KC_XVEL, KC_XDEN, KC_XEOS, KC_COUNT
 };
 
 struct StepBuffers {
@@ -113,8 +121,14 @@ struct StepBuffers {
     float2 *S[7];            // packed half-spectrum scratch arrays
 };
 
+// FFT engines: generic one-butterfly-per-thread Stockham with register arrays
+// of 16 or 32 (any 2^a 3^b 5^c length), or the fixed-width engine with 8 or 16
+// elements per thread (power-of-two lengths, radices 2/4/8/16).
+enum EngId { ENG_G16 = 0, ENG_G32 = 1, ENG_F8 = 2, ENG_F16 = 3 };
+
 struct LaunchCfg {
-    FftPlan px, pxi;         // x forward plan (length M) and its reverse
+    int eng_x, eng_y, eng_z; // EngId per axis
+    FftPlan px, pxi;         // x forward plan (length M) and the plan of the inverse
     FftPlan py, pyi;         // y
     FftPlan pz, pzi;         // z
     int tb_x;                // rows per block in x kernels
@@ -122,12 +136,13 @@ struct LaunchCfg {
     int tb_z;                // columns per block in z kernels
 };
 
-// launchers (kernels.hip) -----------------------------------------------------
+// launchers (kernels_yz.hip, kernels_x.hip, kernels_util.hip) ---------------------
 hipError_t launch_ypass(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
                         float2 *const *fields, int nfields, bool inverse,
                         const Counters *prologue, const SourceDev *src);
 hipError_t launch_zfused(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
-                         int mode, float2 *const *in, float2 *const *out, int which);
+                         int mode, float2 *const *in, float2 *const *out);
+// column kx = 0 (packed kx = 0 / Nyquist) of the fused z pass
 hipError_t launch_zpair(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
                         int mode, float2 *const *in, float2 *const *out);
 hipError_t launch_xvel(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,

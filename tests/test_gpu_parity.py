@@ -256,3 +256,25 @@ def test_parity_tissue_bowl_256_full_size(kw):
     errs, tol = compare_outputs(sim, orc, scen, REPORT)
     for k, e in errs.items():
         assert e <= tol, (k, e)
+
+
+def test_fft_engines_and_schedules_agree(kw):
+    """The same run with the fixed-width engine (default power-of-two plans),
+    other fixed schedules, and the generic engine (radix-32 schedules) must
+    agree to float32 round-off."""
+    A, Simulation = kw
+    scen = sc.small_case(64, 32, 64, seed=4, steps=12, sensor_mask=True)
+    _banner("engines agree")
+    ref = Simulation(scen)
+    ref.step(12)
+    p_ref = ref.gather(A.KW_REC_P_FINAL, device=False)
+    for plans in ([(0, [8, 4]), (1, [8, 4]), (2, [8, 8])],
+                  [(0, [32]), (1, [32]), (2, [32, 2])],
+                  [(0, [2, 16]), (1, [4, 8]), (2, [4, 16])]):
+        sim = Simulation(scen)
+        for axis, rad in plans:
+            sim.set_plan(axis, rad)
+        sim.step(12)
+        e = rel_l2(sim.gather(A.KW_REC_P_FINAL, device=False), p_ref)
+        print("  plans %s rel %.2e" % (plans, e))
+        assert e < 1e-5
