@@ -94,6 +94,9 @@ def load(path: str = LIB_PATH):
     global _lib
     if _lib is not None:
         return _lib
+    # torch first: it brings the HIP runtime the workspace tensors live in, and
+    # libkw.so must bind to that same runtime rather than load a second one
+    import torch  # noqa: F401
     if not os.path.exists(path):
         raise FileNotFoundError("HIP library %s is missing: run paper_1408_4675_amd.build "
                                 "(or __graft_entry__.build()) first" % path)

@@ -1,0 +1,164 @@
+"""FFT schedule autotuner.
+
+For each axis of a grid it times candidate radix schedules (and, for the
+column passes, column-tile widths; for the x rows, rows per block) with the
+library's per-kernel HIP-event profiling, keeps the fastest, and caches the
+choice as JSON keyed by device architecture, axis kind and transform length.
+`Simulation` applies cached choices automatically; without a cache the
+library's built-in defaults are used.  This plays the role that FFT planning
+by measurement plays in the paper's cluster code (Section 3.4), but the search
+space is this library's own: radix factorisations 2/3/4/5/8/16(/32) and tile
+shapes of the LDS-staged passes.
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import os
+from typing import Dict, List, Optional, Sequence, Tuple
+
+CACHE_ENV = "KW_TUNE_CACHE"
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "kw_tune.json")
+
+# kernel classes whose time depends on each axis' schedule
+AXIS_CLASSES = {0: ("xvel", "xden", "xeos"),
+                1: ("ypass_fwd", "ypass_inv"),
+                2: ("zfused_grad", "zfused_div", "zfused_abs", "zpair")}
+
+
+def cache_path() -> str:
+    return os.environ.get(CACHE_ENV, DEFAULT_CACHE)
+
+
+def _arch() -> str:
+    try:
+        import torch
+        return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    except Exception:
+        return "unknown"
+
+
+def load_cache() -> Dict:
+    p = cache_path()
+    if os.path.exists(p):
+        try:
+            with open(p) as fh:
+                return json.load(fh)
+        except (OSError, ValueError):
+            return {}
+    return {}
+
+
+def save_cache(d: Dict):
+    p = cache_path()
+    os.makedirs(os.path.dirname(p), exist_ok=True)
+    tmp = p + ".tmp"
+    with open(tmp, "w") as fh:
+        json.dump(d, fh, indent=1, sort_keys=True)
+    os.replace(tmp, p)
+
+
+def key(axis: int, n: int, arch: Optional[str] = None) -> str:
+    kind = "x" if axis == 0 else "col"
+    return "%s|%s|%d" % (arch or _arch(), kind, n)
+
+
+def lengths(grid) -> Tuple[int, int, int]:
+    """Transform length per axis: nx/2 for the packed x rows, ny, nz."""
+    return (grid.nx // 2, grid.ny, grid.nz)
+
+
+def _factorisations(n: int, radices: Sequence[int], max_passes: int = 4) -> List[List[int]]:
+    out = []
+
+    def rec(m, cur):
+        if m == 1:
+            out.append(list(cur))
+            return
+        if len(cur) >= max_passes:
+            return
+        for r in radices:
+            if m % r == 0 and (not cur or r <= cur[-1]):
+                cur.append(r)
+                rec(m // r, cur)
+                cur.pop()
+    rec(n, [])
+    return out
+
+
+def candidates(axis: int, n: int) -> List[Tuple[List[int], int]]:
+    """(radix schedule, tile) pairs worth timing for one axis."""
+    pow2 = n & (n - 1) == 0
+    if pow2:
+        scheds = _factorisations(n, (16, 8, 4, 2), 4)
+        # keep the shortest schedules (at most one pass more than the minimum)
+        mn = min(len(s) for s in scheds)
+        scheds = [s for s in scheds if len(s) <= mn + 1]
+        if n >= 64:
+            scheds += [s for s in _factorisations(n, (32, 16, 8), 2) if 32 in s]
+    else:
+        scheds = _factorisations(n, (16, 15, 12, 10, 8, 6, 5, 4, 3, 2), 3)
+        mn = min(len(s) for s in scheds)
+        scheds = [s for s in scheds if len(s) == mn][:6]
+    tiles = (0, 4, 8, 16, 32) if axis == 0 else (0, 8, 16, 32)
+    return [(s, t) for s, t in itertools.product(scheds, tiles)]
+
+
+def _time_axis(scen, axis: int, sched: List[int], tile: int, steps: int) -> Optional[float]:
+    from . import _abi as A
+    from .simulation import Simulation
+    try:
+        sim = Simulation(scen, tune=False)
+        sim.set_plan(axis, sched, tile)
+    except A.KwError:
+        return None
+    sim.step(2)
+    sim.synchronize()
+    sim.stats()
+    sim.profile(True)
+    base = sim.stats()["classes"]
+    sim.step(steps)
+    st = sim.stats()["classes"]
+    sim.profile(False)
+    sim.close()
+    return sum(st[c]["ms"] - base[c]["ms"] for c in AXIS_CLASSES[axis]) / steps
+
+
+def tune(scen, axes=(0, 1, 2), steps: int = 4, verbose: bool = True, save: bool = True) -> Dict:
+    """Time every candidate schedule for the requested axes of `scen` and
+    record the fastest in the cache.  Returns {axis: (schedule, tile, ms)}."""
+    cache = load_cache()
+    arch = _arch()
+    result = {}
+    for axis in axes:
+        n = lengths(scen.grid)[axis]
+        best = None
+        for sched, tile in candidates(axis, n):
+            ms = _time_axis(scen, axis, sched, tile, steps)
+            if ms is None:
+                continue
+            if verbose:
+                print("tune axis %d n=%d %-14s tile %2d: %.4f ms/step" % (axis, n, sched, tile, ms),
+                      flush=True)
+            if best is None or ms < best[2]:
+                best = (sched, tile, ms)
+        if best is not None:
+            result[axis] = best
+            cache[key(axis, n, arch)] = dict(radices=best[0], tile=best[1], ms=best[2])
+    if save:
+        save_cache(cache)
+    return result
+
+
+def lookup(grid) -> Dict[int, Tuple[List[int], int]]:
+    """Cached choices for the axes of `grid` ({} when nothing is cached)."""
+    cache = load_cache()
+    if not cache:
+        return {}
+    arch = _arch()
+    out = {}
+    for axis, n in enumerate(lengths(grid)):
+        e = cache.get(key(axis, n, arch))
+        if e:
+            out[axis] = (list(e["radices"]), int(e.get("tile", 0)))
+    return out

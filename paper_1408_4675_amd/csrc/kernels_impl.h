@@ -189,17 +189,21 @@ __device__ __forceinline__ float2 z_operator(const ZArgs &a, int o, int ix, int 
 template <class Eng, int MODE>
 __global__ void __launch_bounds__(512) kw_zfused(ZArgs a) {
     constexpr int E = Eng::E;
-    constexpr int NIN = (MODE == ZM_GRAD) ? 1 : (MODE == ZM_DIV) ? 3 : 2;
     extern __shared__ float2 sh[];
     const int tid = threadIdx.x;
     const int b = tid % a.tb, t = tid / a.tb;
-    const int ny = a.g.ny, nz = a.g.nz, M = a.g.M;
+    const int ny = a.g.ny, M = a.g.M;
     const size_t stride = (size_t)M * ny;
     const ColLds lds{sh, a.tb, b};
     const int blk = blockIdx.x;
     const int cin = Eng::in_count(a.pf, t);
     const int cmid = Eng::out_count(a.pf, t);
     const int cout = Eng::out_count(a.pi, t);
+    // blockIdx.y selects the output; each output has its own blocks (the
+    // gradient's three outputs re-read the one input), which keeps a block to
+    // one forward and one inverse transform and its register use low
+    const int o = blockIdx.y;
+    const int f = (MODE == ZM_GRAD) ? 0 : o;
 
     const int tile = blk % a.ntiles, iy = blk / a.ntiles;
     const int col = tile * a.tb + b;
@@ -207,64 +211,38 @@ __global__ void __launch_bounds__(512) kw_zfused(ZArgs a) {
     const bool st_ok = ok && col != 0;
     const int ix = ok ? col : 0;
     const size_t off = (size_t)iy * M + col;
-#pragma unroll 1
-    for (int f = 0; f < NIN; ++f) {
-        const int salt = f & a.zero;
-        const float2 *twz = a.t.tw_z + salt;
-        float2 v[E];
-        if (ok) {
-            const float2 *src = pick3(a.in, f) + off;
+    float2 v[E];
+    if (ok) {
+        const float2 *src = pick3(a.in, f) + off;
 #pragma unroll
-            for (int m = 0; m < E; ++m)
-                if (m < cin) v[m] = src[(size_t)Eng::in_index(a.pf, t, m) * stride];
-        }
-        Eng::template run<false>(a.pf, twz, t, lds, v);
-        if constexpr (MODE == ZM_GRAD) {
-            float2 vf[E];
+        for (int m = 0; m < E; ++m)
+            if (m < cin) v[m] = src[(size_t)Eng::in_index(a.pf, t, m) * stride];
+    }
+    Eng::template run<false>(a.pf, a.t.tw_z, t, lds, v);
 #pragma unroll
-            for (int m = 0; m < E; ++m) vf[m] = v[m];
-#pragma unroll 1
-            for (int o = 0; o < 3; ++o) {
-                const float2 *twz = a.t.tw_z + (o & a.zero);
+    for (int m = 0; m < E; ++m)
+        if (m < cmid) v[m] = c_mul(v[m], z_operator<MODE>(a, o, ix, iy, Eng::out_index(a.pf, t, m)));
+    Eng::template run<true>(a.pi, a.t.tw_z, t, lds, v);
+    if (st_ok) {
+        float2 *dst = pick3(a.out, o) + off;
 #pragma unroll
-                for (int m = 0; m < E; ++m)
-                    if (m < cmid)
-                        v[m] = c_mul(vf[m], z_operator<MODE>(a, o, ix, iy,
-                                                             Eng::out_index(a.pf, t, m)));
-                Eng::template run<true>(a.pi, twz, t, lds, v);
-                if (st_ok) {
-                    float2 *dst = pick3(a.out, o) + off;
-#pragma unroll
-                    for (int m = 0; m < E; ++m)
-                        if (m < cout) dst[(size_t)Eng::out_index(a.pi, t, m) * stride] = v[m];
-                }
-            }
-        } else {
-#pragma unroll
-            for (int m = 0; m < E; ++m)
-                if (m < cmid)
-                    v[m] = c_mul(v[m], z_operator<MODE>(a, f, ix, iy, Eng::out_index(a.pf, t, m)));
-            Eng::template run<true>(a.pi, twz, t, lds, v);
-            if (st_ok) {
-                float2 *dst = pick3(a.out, f) + off;
-#pragma unroll
-                for (int m = 0; m < E; ++m)
-                    if (m < cout) dst[(size_t)Eng::out_index(a.pi, t, m) * stride] = v[m];
-            }
-        }
+        for (int m = 0; m < E; ++m)
+            if (m < cout) dst[(size_t)Eng::out_index(a.pi, t, m) * stride] = v[m];
     }
 }
 
 template <class Eng, int MODE>
 __global__ void __launch_bounds__(512) kw_zpair(ZArgs a) {
     constexpr int E = Eng::E;
-    constexpr int NIN = (MODE == ZM_GRAD) ? 1 : (MODE == ZM_DIV) ? 3 : 2;
     extern __shared__ float2 sh[];
     const int tid = threadIdx.x;
     const int b = tid % a.tb, t = tid / a.tb;
     const int ny = a.g.ny, nz = a.g.nz, M = a.g.M;
     const size_t stride = (size_t)M * ny;
+    // LDS: [FFT exchange buffer | forward spectra of the block's columns]
     const ColLds lds{sh, a.tb, b};
+    const ColLds spec{sh + (size_t)a.tb * nz, a.tb, b};
+    const ColLds partner{sh + (size_t)a.tb * nz, a.tb, b ^ 1};
     const int cin = Eng::in_count(a.pf, t);
     const int cmid = Eng::out_count(a.pf, t);
     const int cout = Eng::out_count(a.pi, t);
@@ -276,55 +254,40 @@ __global__ void __launch_bounds__(512) kw_zpair(ZArgs a) {
     const int iy = side ? ky1 : ky0;
     const bool store = valid && (side == 0 || ky1 != ky0);
     const size_t off = (size_t)iy * M;
-    const ColLds partner{sh, a.tb, b ^ 1};
-#pragma unroll 1
-    for (int f = 0; f < NIN; ++f) {
-        float2 v[E];
-        if (valid) {
-            const float2 *src = pick3(a.in, f) + off;
-#pragma unroll
-            for (int m = 0; m < E; ++m)
-                if (m < cin) v[m] = src[(size_t)Eng::in_index(a.pf, t, m) * stride];
-        }
-        Eng::template run<false>(a.pf, a.t.tw_z, t, lds, v);
+    const int o = blockIdx.y;                       // output (see kw_zfused)
+    const int f = (MODE == ZM_GRAD) ? 0 : o;
+    float2 v[E];
+    if (valid) {
+        const float2 *src = pick3(a.in, f) + off;
 #pragma unroll
         for (int m = 0; m < E; ++m)
-            if (m < cmid) lds.st(Eng::out_index(a.pf, t, m), v[m]);
-        __syncthreads();
-        float2 va[E], vb[E];
+            if (m < cin) v[m] = src[(size_t)Eng::in_index(a.pf, t, m) * stride];
+    }
+    Eng::template run<false>(a.pf, a.t.tw_z, t, lds, v);
 #pragma unroll
-        for (int m = 0; m < E; ++m) {
-            if (m < cmid) {
-                const int iz = Eng::out_index(a.pf, t, m);
-                const float2 c = v[m];
-                const float2 pc = c_conj(partner.ld((nz - iz) % nz));
-                va[m] = c_scale(c_add(c, pc), 0.5f);
-                const float2 d = c_sub(c, pc);
-                vb[m] = make_float2(0.5f * d.y, -0.5f * d.x);     // (c - pc) / (2i)
-            }
+    for (int m = 0; m < E; ++m)
+        if (m < cmid) spec.st(Eng::out_index(a.pf, t, m), v[m]);
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        if (m < cmid) {
+            const int iz = Eng::out_index(a.pf, t, m);
+            const float2 c = v[m];
+            const float2 pc = c_conj(partner.ld((nz - iz) % nz));
+            const float2 va = c_scale(c_add(c, pc), 0.5f);
+            const float2 d = c_sub(c, pc);
+            const float2 vb = make_float2(0.5f * d.y, -0.5f * d.x);   // (c - pc) / (2i)
+            const float2 ya = c_mul(va, z_operator<MODE>(a, o, 0, iy, iz));
+            const float2 yb = c_mul(vb, z_operator<MODE>(a, o, M, iy, iz));
+            v[m] = make_float2(ya.x - yb.y, ya.y + yb.x);   // ya + i yb
         }
-        __syncthreads();
-        constexpr int NO = (MODE == ZM_GRAD) ? 3 : 1;
-#pragma unroll 1
-        for (int oo = 0; oo < NO; ++oo) {
-            const int o = (MODE == ZM_GRAD) ? oo : f;
+    }
+    Eng::template run<true>(a.pi, a.t.tw_z, t, lds, v);
+    if (store) {
+        float2 *dst = pick3(a.out, o) + off;
 #pragma unroll
-            for (int m = 0; m < E; ++m) {
-                if (m < cmid) {
-                    const int iz = Eng::out_index(a.pf, t, m);
-                    const float2 ya = c_mul(va[m], z_operator<MODE>(a, o, 0, iy, iz));
-                    const float2 yb = c_mul(vb[m], z_operator<MODE>(a, o, M, iy, iz));
-                    v[m] = make_float2(ya.x - yb.y, ya.y + yb.x);   // ya + i yb
-                }
-            }
-            Eng::template run<true>(a.pi, a.t.tw_z, t, lds, v);
-            if (store) {
-                float2 *dst = pick3(a.out, o) + off;
-#pragma unroll
-                for (int m = 0; m < E; ++m)
-                    if (m < cout) dst[(size_t)Eng::out_index(a.pi, t, m) * stride] = v[m];
-            }
-        }
+        for (int m = 0; m < E; ++m)
+            if (m < cout) dst[(size_t)Eng::out_index(a.pi, t, m) * stride] = v[m];
     }
 }
 
@@ -434,44 +397,39 @@ __device__ __forceinline__ void row_r2c(const XArgs &a, float2 *__restrict__ row
     const int cupd = Eng::out_count(a.pi, t);                          \
     (void)nx; (void)rbase; (void)cupd;
 
+// The three velocity components are independent: blockIdx.y selects one.
 template <class Eng>
 __global__ void __launch_bounds__(512) kw_xvel(XArgs a) {
     KW_XPROLOGUE
     const int iy = rr % a.g.ny, iz = rr / a.g.ny;
-#pragma unroll 1
-    for (int xi = 0; xi < 3; ++xi) {
-        // an opaque zero that depends on xi keeps the compiler from hoisting
-        // the loop-invariant table loads out of the loop (which would keep
-        // them live across all three fields and spill registers)
-        const int salt = xi & a.zero;
-        float2 v[E];
-        row_c2r<Eng>(a, pick3(a.Sin, xi) + (size_t)rr * M, ok, t, lds, v, salt);
-        if (ok) {
-            float *u = pick3(a.fld, xi);
-            const Coef dtr = xi == 0 ? a.m.dtr[0] : xi == 1 ? a.m.dtr[1] : a.m.dtr[2];
-            const float qy = a.t.pml_sy[iy], qz = a.t.pml_sz[iz];
+    const int xi = blockIdx.y;
+    float2 v[E];
+    row_c2r<Eng>(a, pick3(a.Sin, xi) + (size_t)rr * M, ok, t, lds, v);
+    if (ok) {
+        float *u = pick3(a.fld, xi);
+        const Coef dtr = xi == 0 ? a.m.dtr[0] : xi == 1 ? a.m.dtr[1] : a.m.dtr[2];
+        const float qy = a.t.pml_sy[iy], qz = a.t.pml_sz[iz];
 #pragma unroll
-            for (int m = 0; m < E; ++m) {
-                if (m < cupd) {
-                    const int x = 2 * Eng::out_index(a.pi, t, m);
-                    const size_t i = rbase + x;
-                    float2 q;
-                    if (xi == 0) q = make_float2(a.t.pml_sx[x + salt], a.t.pml_sx[x + 1 + salt]);
-                    else if (xi == 1) q = make_float2(qy, qy);
-                    else q = make_float2(qz, qz);
-                    const float2 d = coef2_at(dtr, i);
-                    const float2 u0 = ld2(u, i);
-                    const float2 g = v[m];
-                    float2 un;
-                    un.x = q.x * (q.x * u0.x - d.x * g.x);
-                    un.y = q.y * (q.y * u0.y - d.y * g.y);
-                    st2(u, i, un);
-                    v[m] = un;
-                }
+        for (int m = 0; m < E; ++m) {
+            if (m < cupd) {
+                const int x = 2 * Eng::out_index(a.pi, t, m);
+                const size_t i = rbase + x;
+                float2 q;
+                if (xi == 0) q = make_float2(a.t.pml_sx[x], a.t.pml_sx[x + 1]);
+                else if (xi == 1) q = make_float2(qy, qy);
+                else q = make_float2(qz, qz);
+                const float2 d = coef2_at(dtr, i);
+                const float2 u0 = ld2(u, i);
+                const float2 g = v[m];
+                float2 un;
+                un.x = q.x * (q.x * u0.x - d.x * g.x);
+                un.y = q.y * (q.y * u0.y - d.y * g.y);
+                st2(u, i, un);
+                v[m] = un;
             }
         }
-        row_r2c<Eng>(a, pick3(a.Sout, xi) + (size_t)rr * M, ok, t, lds, v, salt);
     }
+    row_r2c<Eng>(a, pick3(a.Sout, xi) + (size_t)rr * M, ok, t, lds, v);
 }
 
 // Source values of the rows of this block, scattered into a per-row LDS line

@@ -17,9 +17,10 @@ static inline size_t x_lds(const GridDev &g, const LaunchCfg &c, bool line) {
     if (line) n += (size_t)c.tb_x * g.nx * sizeof(float);
     return n;
 }
-#define KW_XLAUNCH(KERNEL, LINE)                                                     \
+#define KW_XLAUNCH(KERNEL, LINE) KW_XLAUNCH_N(KERNEL, LINE, 1)
+#define KW_XLAUNCH_N(KERNEL, LINE, NY)                                               \
     do {                                                                             \
-        dim3 grid((g.rows + c.tb_x - 1) / c.tb_x);                                   \
+        dim3 grid((g.rows + c.tb_x - 1) / c.tb_x, NY);                               \
         dim3 block(c.tb_x * c.px.L);                                                 \
         size_t lds = x_lds(g, c, LINE);                                              \
         KW_ENGINE_SWITCH(c.eng_x, hipLaunchKernelGGL((KERNEL<Eng>), grid, block, lds, s, a)); \
@@ -34,7 +35,7 @@ hipError_t launch_xvel(hipStream_t s, const GridDev &g, const LaunchCfg &c, cons
         a.Sout[i] = S[i];
         a.fld[i] = u[i];
     }
-    KW_XLAUNCH(kw_xvel, false);
+    KW_XLAUNCH_N(kw_xvel, false, 3);
     return hipGetLastError();
 }
 

@@ -93,7 +93,7 @@ def workspace_size(sc: Scenario) -> int:
 
 class Simulation:
     def __init__(self, sc: Scenario, device: str = "cuda", stream: Optional[torch.cuda.Stream] = None,
-                 graph_steps: Optional[int] = None):
+                 graph_steps: Optional[int] = None, tune: bool = True):
         self.lib = A.load()
         self.scenario = sc
         self.device = torch.device(device)
@@ -116,6 +116,16 @@ class Simulation:
         self.npts = sc.grid.npts
         if graph_steps is not None:
             A.check(self.lib.kw_set_graph(self.handle, int(graph_steps)))
+        self.plans = {}
+        if tune:
+            # schedules chosen by the autotuner for these transform lengths, if cached
+            from .autotune import lookup
+            for axis, (rad, tile) in lookup(sc.grid).items():
+                try:
+                    self.set_plan(axis, rad, tile)
+                    self.plans[axis] = (rad, tile)
+                except A.KwError:
+                    pass
 
     # ------------------------------------------------------------------
     def step(self, n: int = 1):

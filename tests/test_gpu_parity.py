@@ -278,3 +278,45 @@ def test_fft_engines_and_schedules_agree(kw):
         e = rel_l2(sim.gather(A.KW_REC_P_FINAL, device=False), p_ref)
         print("  plans %s rel %.2e" % (plans, e))
         assert e < 1e-5
+
+
+LONG = [(16, 8, 1024), (16, 1024, 8), (1024, 8, 8), (16, 8, 512), (32, 512, 6), (512, 6, 10),
+        (16, 8, 256), (24, 10, 960)]
+
+
+@pytest.mark.parametrize("shape", LONG, ids=["%dx%dx%d" % s for s in LONG])
+def test_parity_long_axes(kw, shape):
+    """Transforms of 256-1024 points (up to 64 threads per transform and three
+    radix passes), with a heterogeneous nonlinear absorbing medium and a PML."""
+    nx, ny, nz = shape
+    scen = sc.small_case(nx, ny, nz, seed=9, heterogeneous=True, nonlinear=True, absorbing=True,
+                         pml=2, steps=6, sensor_mask=False)
+    sim, orc = _run_both(kw, scen, 6)
+    errs, tol = compare_outputs(sim, orc, scen, REPORT)
+    for k, e in errs.items():
+        assert e <= tol, (k, e)
+
+
+@pytest.mark.slow
+def test_water_bowl_1024_full_size_properties(kw):
+    """The 1024^3 homogeneous water grid with the 3 MHz bowl, in the launch
+    configuration bench.py times: the pressure stays finite and bounded, and
+    it keeps the x <-> y exchange symmetry of the set-up (axis-centred bowl,
+    isotropic spacing; the symmetry the scheme preserves exactly, pinned on the
+    oracle) to float32 round-off.  The oracle itself cannot run at this size."""
+    A, Simulation = kw
+    scen = sc.water_bowl_large(n=1024, steps=40)
+    _banner("water bowl 1024^3, 40 steps")
+    sim = Simulation(scen)
+    sim.step(40)
+    st = sim.stats()
+    assert st["nonfinite_step"] == -1
+    p = sim.get_field(A.KW_FIELD_P).reshape(1024, 1024, 1024)
+    pmax = float(np.abs(p).max())
+    print("  max|p| %.3e" % pmax)
+    assert 1e5 < pmax < 2e7
+    # symmetry on a band of z-planes through the source (keeps host memory small)
+    band = p[100:260]
+    err = float(np.abs(band - band.transpose(0, 2, 1)).max() / np.abs(band).max())
+    print("  x<->y symmetry error %.2e" % err)
+    assert err < 1e-4
