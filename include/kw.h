@@ -136,7 +136,7 @@ typedef struct kw_stats_t {
     char    class_name[16][24];    /* kernel class names                              */
     double  class_ms[16];          /* summed device time per class (profiling on)     */
     int64_t class_launches[16];    /* launches per class while profiling              */
-    double  class_bytes[16];       /* algorithmic HBM bytes per launch of the class   */
+    double  class_bytes[16];       /* mean algorithmic HBM bytes per launch of the class */
 } kw_stats_t;
 
 /* Device bytes needed by a simulation with these inputs (the same number is

@@ -59,8 +59,19 @@ def save_cache(d: Dict):
 
 
 def key(axis: int, n: int, arch: Optional[str] = None) -> str:
-    kind = "x" if axis == 0 else "col"
-    return "%s|%s|%d" % (arch or _arch(), kind, n)
+    return "%s|%s|%d" % (arch or _arch(), "xyz"[axis], n)
+
+
+SHIPPED_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning")
+
+
+def shipped_table(arch: Optional[str] = None) -> Dict:
+    """Choices measured for this package on `arch` and shipped with it."""
+    p = os.path.join(SHIPPED_DIR, "%s.json" % (arch or _arch()))
+    if os.path.exists(p):
+        with open(p) as fh:
+            return json.load(fh)
+    return {}
 
 
 def lengths(grid) -> Tuple[int, int, int]:
@@ -151,14 +162,15 @@ def tune(scen, axes=(0, 1, 2), steps: int = 4, verbose: bool = True, save: bool 
 
 
 def lookup(grid) -> Dict[int, Tuple[List[int], int]]:
-    """Cached choices for the axes of `grid` ({} when nothing is cached)."""
-    cache = load_cache()
-    if not cache:
-        return {}
+    """Choices for the axes of `grid`: the user's cache first, then the table
+    shipped with the package ({} when neither has an entry)."""
     arch = _arch()
+    tables = (load_cache(), shipped_table(arch))
     out = {}
     for axis, n in enumerate(lengths(grid)):
-        e = cache.get(key(axis, n, arch))
-        if e:
-            out[axis] = (list(e["radices"]), int(e.get("tile", 0)))
+        for tab in tables:
+            e = tab.get(key(axis, n, arch))
+            if e:
+                out[axis] = (list(e["radices"]), int(e.get("tile", 0)))
+                break
     return out

@@ -498,7 +498,7 @@ void resolve_profile(kw_sim *s) {
         if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
             s->class_ms[r.cls] += ms;
             s->class_n[r.cls] += 1;
-            s->class_bytes[r.cls] = r.bytes;
+            s->class_bytes[r.cls] += r.bytes;
         }
         s->pool.push_back(r.a);
         s->pool.push_back(r.b);
@@ -1212,7 +1212,7 @@ int kw_stats(kw_sim *s, kw_stats_t *out) {
         std::snprintf(out->class_name[i], sizeof out->class_name[i], "%s", kClassNames[i]);
         out->class_ms[i] = s->class_ms[i];
         out->class_launches[i] = s->class_n[i];
-        out->class_bytes[i] = s->class_bytes[i];
+        out->class_bytes[i] = s->class_n[i] > 0 ? s->class_bytes[i] / (double)s->class_n[i] : 0.0;
     }
     return KW_OK;
 }
