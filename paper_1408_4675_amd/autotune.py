@@ -23,7 +23,7 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "kw_tune.json")
 # kernel classes whose time depends on each axis' schedule
 AXIS_CLASSES = {0: ("xvel", "xden", "xeos"),
                 1: ("ypass_fwd", "ypass_inv"),
-                2: ("zfused_grad", "zfused_div", "zfused_abs", "zpair")}
+                2: ("zfused_grad", "zfused_div", "zfused_abs")}
 
 
 def cache_path() -> str:

@@ -428,9 +428,6 @@ struct kw_sim {
     int record_start;
     long steps = 0;
     bool stepped = false;
-    // helper stream for the column-0 pair kernels, which overlap the fused z pass
-    hipStream_t aux = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // graphs
     int graph_steps = 8;
     hipGraphExec_t graph_exec = nullptr;
@@ -458,8 +455,7 @@ struct kw_sim {
 namespace {
 
 const char *kClassNames[KC_COUNT] = {"ypass_fwd", "ypass_inv", "zfused_grad", "zfused_div",
-                                     "zfused_abs", "zpair",     "xvel",        "xden",
-                                     "xeos"};
+                                     "zfused_abs", "xvel",      "xden",        "xeos"};
 
 hipEvent_t take_event(kw_sim *s) {
     if (!s->pool.empty()) {
@@ -492,7 +488,6 @@ hipError_t launch(kw_sim *s, int cls, double nbytes, F fn) {
 void resolve_profile(kw_sim *s) {
     if (s->recs.empty()) return;
     (void)hipStreamSynchronize(s->stream);
-    if (s->aux) (void)hipStreamSynchronize(s->aux);
     for (auto &r : s->recs) {
         float ms = 0.0f;
         if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
@@ -534,39 +529,16 @@ hipError_t enqueue_step(kw_sim *s) {
         ++nk;                                                                   \
     } while (0)
 
-    // zfused (all columns but 0) and zpair (column 0) read the same input and
-    // write disjoint outputs: run zpair on the helper stream, joined before
-    // the next kernel (serial while profiling, so that every kernel is timed)
-    auto zpair = [&](int mode, float2 *const *in, float2 *const *out) -> hipError_t {
-        ++nk;
-        if (!s->aux)
-            return launch(s, KC_ZPAIR, 0.0, [&] { return launch_zpair(st, g, c, t, mode, in, out); });
-        hipError_t r = hipEventRecord(s->ev_fork, st);
-        if (r == hipSuccess) r = hipStreamWaitEvent(s->aux, s->ev_fork, 0);
-        if (r == hipSuccess)
-            r = launch_on(s, s->aux, KC_ZPAIR, 0.0,
-                          [&] { return launch_zpair(s->aux, g, c, t, mode, in, out); });
-        if (r == hipSuccess) r = hipEventRecord(s->ev_join, s->aux);
-        return r;
-    };
-    auto join = [&]() -> hipError_t {
-        if (!s->aux) return hipSuccess;
-        return hipStreamWaitEvent(st, s->ev_join, 0);
-    };
     float2 *s0[1] = {S[0]};
     float2 *s123[3] = {S[1], S[2], S[3]};
     float2 *s456[3] = {S[4], S[5], S[6]};
     KW_L(KC_YFWD, 2, launch_ypass(st, g, c, t, s0, 1, false, &s->counters, &s->src));
-    if ((e = zpair(0, s0, s123)) != hipSuccess) return e;
     KW_L(KC_ZGRAD, 4, launch_zfused(st, g, c, t, 0, s0, s123));
-    if ((e = join()) != hipSuccess) return e;
     KW_L(KC_YINV, 6, launch_ypass(st, g, c, t, s123, 3, true, nullptr, nullptr));
     KW_L(KC_XVEL, 12 + (ms.het[MED_DTRX] ? 3 : 0),
          launch_xvel(st, g, c, t, s->med, s123, s->buf.u));
     KW_L(KC_YFWD, 6, launch_ypass(st, g, c, t, s123, 3, false, nullptr, nullptr));
-    if ((e = zpair(1, s123, s456)) != hipSuccess) return e;
     KW_L(KC_ZDIV, 6, launch_zfused(st, g, c, t, 1, s123, s456));
-    if ((e = join()) != hipSuccess) return e;
     KW_L(KC_YINV, 6, launch_ypass(st, g, c, t, s456, 3, true, nullptr, nullptr));
     if (absorbing) {
         float2 *out2[2] = {S[1], S[2]};
@@ -576,10 +548,8 @@ hipError_t enqueue_step(kw_sim *s) {
         float2 *s12[2] = {S[1], S[2]};
         float2 *s45[2] = {S[4], S[5]};
         KW_L(KC_YFWD, 4, launch_ypass(st, g, c, t, s12, 2, false, nullptr, nullptr));
-        if ((e = zpair(2, s12, s45)) != hipSuccess) return e;
         KW_L(KC_ZABS, 4, launch_zfused(st, g, c, t, 2, s12, s45));
-        if ((e = join()) != hipSuccess) return e;
-            KW_L(KC_YINV, 4, launch_ypass(st, g, c, t, s45, 2, true, nullptr, nullptr));
+        KW_L(KC_YINV, 4, launch_ypass(st, g, c, t, s45, 2, true, nullptr, nullptr));
         const double med_units = (ms.het[MED_C0SQ] ? 1 : 0) + (ms.het[MED_NL] ? 1 : 0) +
                                  (ms.het[MED_TA] ? 2 : 0);
         KW_L(KC_XEOS, 4 + med_units + sens_units,
@@ -642,6 +612,10 @@ int pick_tiles(kw_sim *s, int tile_y, int tile_z) {
         return (size_t)tb * (g.M + (g.M >> 4) + 1) * sizeof(float2) + (size_t)tb * g.nx * sizeof(float);
     };
     while (c.tb_x > 1 && x_lds_bytes(c.tb_x) > 64 * 1024) c.tb_x /= 2;
+    c.tb_den = std::max(1, 512 / (3 * c.px.L));
+    while (c.tb_den > 1 && den_lds_bytes(g.M, g.nx, c.tb_den) > 64 * 1024) --c.tb_den;
+    if (3 * c.px.L > 512 || den_lds_bytes(g.M, g.nx, c.tb_den) > 64 * 1024)
+        return fail(KW_EUNSUPPORTED, "density pass does not fit a block (nx = %d)", g.nx);
     auto col_tile = [&](int n, int L, int req) {
         if (req > 0) return req;
         int tb = 16;
@@ -650,8 +624,6 @@ int pick_tiles(kw_sim *s, int tile_y, int tile_z) {
     };
     c.tb_y = col_tile(g.ny, c.py.L, tile_y);
     c.tb_z = col_tile(g.nz, c.pz.L, tile_z);
-    if (c.tb_z < 2 || (c.tb_z & 1))
-        return fail(KW_EUNSUPPORTED, "z column tile must be even and >= 2 (got %d)", c.tb_z);
     const size_t xl = (size_t)c.tb_x * (g.M + (g.M >> 4) + 1) * sizeof(float2) +
                       (size_t)c.tb_x * g.nx * sizeof(float);
     int rc;
@@ -667,9 +639,6 @@ void release(kw_sim *s) {
     resolve_profile(s);
     drop_graph(s);
     for (hipEvent_t e : s->pool) (void)hipEventDestroy(e);
-    if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
-    if (s->ev_join) (void)hipEventDestroy(s->ev_join);
-    if (s->aux) (void)hipStreamDestroy(s->aux);
     delete s;
 }
 
@@ -997,10 +966,6 @@ int kw_create(const kw_grid *grid, const kw_medium *medium, const kw_source *sou
     int dev_count = 0;
     if (hipGetDeviceCount(&dev_count) != hipSuccess || dev_count < 1)
         return bail(fail(KW_EDEVICE, "no HIP device"));
-    if (hipStreamCreateWithFlags(&s->aux, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming) != hipSuccess)
-        return bail(fail(KW_EDEVICE, "could not create the helper stream"));
     for (auto &u : up) {
         hipError_t e = hipMemcpyAsync(s->ws + u.first, u.second.data(), u.second.size(),
                                       hipMemcpyHostToDevice, s->stream);
@@ -1261,7 +1226,6 @@ int kw_set_plan(kw_sim *s, int axis, const int32_t *radices, int32_t n_radices, 
 int kw_destroy(kw_sim *s) {
     if (!s) return KW_OK;
     (void)hipStreamSynchronize(s->stream);
-    if (s->aux) (void)hipStreamSynchronize(s->aux);
     release(s);
     return KW_OK;
 }

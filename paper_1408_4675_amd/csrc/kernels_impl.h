@@ -8,8 +8,9 @@
 // first (kx = 0) and last (Nyquist) are real; they are packed into one complex
 // value X0 + i XN at column 0, so a spectrum row has exactly the byte size of a
 // real row.  The y and z transforms are linear and carry the packed column
-// along; the kw_zpair kernel separates it again for column 0 before
-// applying the k-space operators, which differ between kx = 0 and Nyquist.
+// along (the y pass stores it unpacked between its forward and inverse
+// transforms, see col0_type), and the fused z pass applies to each part the
+// operator of its own kx (0 or Nyquist).
 //
 // One step (absorbing case; six forward and eight inverse 3D transforms, in
 // the order of Section 3.4):
@@ -84,6 +85,32 @@ __device__ __forceinline__ float kappa_of_x2(float x2) {
 }
 
 // ---------------------------------------------------------------------------
+// Column kx = 0 of a spectrum holds X0 + i XN (the kx = 0 and Nyquist parts of
+// the x transform, both real functions of (y, z)).  Their y transforms A(ky),
+// B(ky) are Hermitian in ky, so between the forward and the inverse y pass
+// column 0 is stored unpacked, with h = (ny - 1) / 2:
+//   row 0 (and row ny/2 for even ny): A + i B as computed (there A and B are
+//                                      real functions of z);
+//   rows 1..h:                         A(ky = row);
+//   rows ny-h..ny-1:                   B(ky = row - (ny - 1 - h)).
+// The fused z pass then treats these rows as ordinary columns (kx = 0 for A,
+// the Nyquist kx for B) and separates A and B of rows 0 and ny/2 with the
+// kz <-> -kz partner in the same column.
+// ---------------------------------------------------------------------------
+enum { C0_DOUBLE = 0, C0_A = 1, C0_B = 2 };
+__device__ __forceinline__ int col0_type(int r, int ny) {
+    const int h = (ny - 1) / 2;
+    if (r == 0 || (!(ny & 1) && r == ny / 2)) return C0_DOUBLE;
+    return r <= h ? C0_A : C0_B;
+}
+// ky index of row r of the unpacked column 0
+__device__ __forceinline__ int col0_ky(int r, int ny) {
+    const int h = (ny - 1) / 2;
+    if (r == 0 || r <= h || (!(ny & 1) && r == ny / 2)) return r;
+    return r - (ny - 1 - h);
+}
+
+// ---------------------------------------------------------------------------
 // y pass: in-place column FFTs of up to three spectra
 // ---------------------------------------------------------------------------
 struct YArgs {
@@ -127,14 +154,75 @@ __global__ void __launch_bounds__(512) kw_ypass(YArgs a) {
     }
 
     float2 v[E];
+    const int ny = a.ny, h = (ny - 1) / 2;
+    const ColLds lds{sh, a.tb, b};
     const int cin = Eng::in_count(a.plan, t);
     if (ok) {
 #pragma unroll
         for (int m = 0; m < E; ++m)
             if (m < cin) v[m] = base[(size_t)Eng::in_index(a.plan, t, m) * stride];
     }
-    Eng::template run<INV>(a.plan, a.tw, t, ColLds{sh, a.tb, b}, v);
+    const bool tile0 = blockIdx.x == 0;          // block-uniform
+    if (INV && tile0) {
+        // repack column 0: C(ky) = A(ky) + i B(ky), using A(-ky) = conj A(ky)
+        if (b == 0) {
+#pragma unroll
+            for (int m = 0; m < E; ++m)
+                if (m < cin) lds.st(Eng::in_index(a.plan, t, m), v[m]);
+        }
+        __syncthreads();
+        if (b == 0) {
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                if (m < cin) {
+                    const int ky = Eng::in_index(a.plan, t, m);
+                    if (col0_type(ky, ny) != C0_DOUBLE) {
+                        const bool neg = ky > h;                 // ky = ny - j, j = 1..h
+                        const int j = neg ? ny - ky : ky;
+                        float2 A = lds.ld(j), B = lds.ld(ny - 1 - h + j);
+                        if (neg) {
+                            A = c_conj(A);
+                            B = c_conj(B);
+                        }
+                        v[m] = make_float2(A.x - B.y, A.y + B.x);   // A + i B
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    Eng::template run<INV>(a.plan, a.tw, t, lds, v);
     const int cout = Eng::out_count(a.plan, t);
+    if (!INV && tile0) {
+        // unpack column 0 into A (rows 1..h) and B (rows ny-h..ny-1)
+        if (b == 0) {
+#pragma unroll
+            for (int m = 0; m < E; ++m)
+                if (m < cout) lds.st(Eng::out_index(a.plan, t, m), v[m]);
+        }
+        __syncthreads();
+        if (b == 0) {
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                if (m < cout) {
+                    const int r = Eng::out_index(a.plan, t, m);
+                    const int type = col0_type(r, ny);
+                    if (type != C0_DOUBLE) {
+                        const int j = col0_ky(r, ny);
+                        const float2 c = lds.ld(j);
+                        const float2 pc = c_conj(lds.ld(ny - j));
+                        if (type == C0_A) {
+                            v[m] = c_scale(c_add(c, pc), 0.5f);                 // (C + conj C(-ky)) / 2
+                        } else {
+                            const float2 d = c_sub(c, pc);
+                            v[m] = make_float2(0.5f * d.y, -0.5f * d.x);        // (C - conj C(-ky)) / 2i
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
     if (ok) {
 #pragma unroll
         for (int m = 0; m < E; ++m)
@@ -178,14 +266,13 @@ __device__ __forceinline__ float2 z_operator(const ZArgs &a, int o, int ix, int 
     }
 }
 
-// kw_zfused: a block handles a tile of tb columns of one ky row (column 0 is
-// skipped on store); kw_zpair handles column 0: it holds X0 + i XN
-// (kx = 0 part and Nyquist part, both real before the y/z transforms).  After
-// the forward z transform the parts are separated with the conjugate-symmetric
-// partner at (-ky, -kz):
-//   A = (C(ky,kz) + conj C(-ky,-kz)) / 2,   B = (C(ky,kz) - conj C(-ky,-kz)) / 2i
-// each gets its own operator and the results are repacked as A' + i B'.  A pair
-// block holds tb/2 pairs of rows (ky, -ky) in adjacent columns of its tile.
+// kw_zfused: a block handles a tile of tb columns of one ky row, for one
+// output (blockIdx.y).  Column 0 arrives unpacked by the y pass: an A row takes
+// the operator of kx = 0 at its own ky, a B row the operator of the Nyquist kx.
+// Rows 0 and ny/2 still hold A + i B with A, B real in z; after the forward z
+// transform the two parts are separated with the partner at -kz,
+//   A = (C(kz) + conj C(-kz)) / 2,   B = (C(kz) - conj C(-kz)) / 2i,
+// each gets its own operator, and the results are repacked as A' + i B'.
 template <class Eng, int MODE>
 __global__ void __launch_bounds__(512) kw_zfused(ZArgs a) {
     constexpr int E = Eng::E;
@@ -208,9 +295,16 @@ __global__ void __launch_bounds__(512) kw_zfused(ZArgs a) {
     const int tile = blk % a.ntiles, iy = blk / a.ntiles;
     const int col = tile * a.tb + b;
     const bool ok = col < M;
-    const bool st_ok = ok && col != 0;
-    const int ix = ok ? col : 0;
     const size_t off = (size_t)iy * M + col;
+    // column 0 of this row (see col0_type): A rows take kx = 0, B rows the
+    // Nyquist kx, and the double rows are split with their kz <-> -kz partner
+    const int c0type = col0_type(iy, ny);
+    const bool pairing = tile == 0 && c0type == C0_DOUBLE;       // block-uniform
+    int ix = ok ? col : 0, iyk = iy;
+    if (col == 0 && c0type != C0_DOUBLE) {
+        ix = (c0type == C0_A) ? 0 : M;
+        iyk = col0_ky(iy, ny);
+    }
     float2 v[E];
     if (ok) {
         const float2 *src = pick3(a.in, f) + off;
@@ -219,71 +313,50 @@ __global__ void __launch_bounds__(512) kw_zfused(ZArgs a) {
             if (m < cin) v[m] = src[(size_t)Eng::in_index(a.pf, t, m) * stride];
     }
     Eng::template run<false>(a.pf, a.t.tw_z, t, lds, v);
-#pragma unroll
-    for (int m = 0; m < E; ++m)
-        if (m < cmid) v[m] = c_mul(v[m], z_operator<MODE>(a, o, ix, iy, Eng::out_index(a.pf, t, m)));
-    Eng::template run<true>(a.pi, a.t.tw_z, t, lds, v);
-    if (st_ok) {
-        float2 *dst = pick3(a.out, o) + off;
+    if (pairing && b == 0) {
+        // the raw spectrum of the double row goes to LDS column 0 (free after
+        // the transform's trailing barrier) for the pair loop below
 #pragma unroll
         for (int m = 0; m < E; ++m)
-            if (m < cout) dst[(size_t)Eng::out_index(a.pi, t, m) * stride] = v[m];
+            if (m < cmid) lds.st(Eng::out_index(a.pf, t, m), v[m]);
     }
-}
-
-template <class Eng, int MODE>
-__global__ void __launch_bounds__(512) kw_zpair(ZArgs a) {
-    constexpr int E = Eng::E;
-    extern __shared__ float2 sh[];
-    const int tid = threadIdx.x;
-    const int b = tid % a.tb, t = tid / a.tb;
-    const int ny = a.g.ny, nz = a.g.nz, M = a.g.M;
-    const size_t stride = (size_t)M * ny;
-    // LDS: [FFT exchange buffer | forward spectra of the block's columns]
-    const ColLds lds{sh, a.tb, b};
-    const ColLds spec{sh + (size_t)a.tb * nz, a.tb, b};
-    const ColLds partner{sh + (size_t)a.tb * nz, a.tb, b ^ 1};
-    const int cin = Eng::in_count(a.pf, t);
-    const int cmid = Eng::out_count(a.pf, t);
-    const int cout = Eng::out_count(a.pi, t);
-    const int side = b & 1;
-    const int pair = blockIdx.x * (a.tb / 2) + (b >> 1);
-    const bool valid = (b < (a.tb & ~1)) && pair <= ny / 2;
-    const int ky0 = valid ? pair : 0;
-    const int ky1 = (ny - ky0) % ny;
-    const int iy = side ? ky1 : ky0;
-    const bool store = valid && (side == 0 || ky1 != ky0);
-    const size_t off = (size_t)iy * M;
-    const int o = blockIdx.y;                       // output (see kw_zfused)
-    const int f = (MODE == ZM_GRAD) ? 0 : o;
-    float2 v[E];
-    if (valid) {
-        const float2 *src = pick3(a.in, f) + off;
-#pragma unroll
-        for (int m = 0; m < E; ++m)
-            if (m < cin) v[m] = src[(size_t)Eng::in_index(a.pf, t, m) * stride];
-    }
-    Eng::template run<false>(a.pf, a.t.tw_z, t, lds, v);
 #pragma unroll
     for (int m = 0; m < E; ++m)
-        if (m < cmid) spec.st(Eng::out_index(a.pf, t, m), v[m]);
-    __syncthreads();
-#pragma unroll
-    for (int m = 0; m < E; ++m) {
-        if (m < cmid) {
-            const int iz = Eng::out_index(a.pf, t, m);
-            const float2 c = v[m];
-            const float2 pc = c_conj(partner.ld((nz - iz) % nz));
-            const float2 va = c_scale(c_add(c, pc), 0.5f);
-            const float2 d = c_sub(c, pc);
-            const float2 vb = make_float2(0.5f * d.y, -0.5f * d.x);   // (c - pc) / (2i)
-            const float2 ya = c_mul(va, z_operator<MODE>(a, o, 0, iy, iz));
-            const float2 yb = c_mul(vb, z_operator<MODE>(a, o, M, iy, iz));
-            v[m] = make_float2(ya.x - yb.y, ya.y + yb.x);   // ya + i yb
+        if (m < cmid)
+            v[m] = c_mul(v[m], z_operator<MODE>(a, o, ix, iyk, Eng::out_index(a.pf, t, m)));
+    if (pairing) {
+        // (kz, -kz) pairs of the double row, one pair per iteration and thread,
+        // updated in place in LDS (a pair is read and written by one thread)
+        __syncthreads();
+        if (b == 0) {
+            const int nz = a.g.nz, nth = blockDim.x / a.tb;
+            for (int iz = t; iz <= nz / 2; iz += nth) {
+                const int jz = (nz - iz) % nz;
+                const float2 c1 = lds.ld(iz), c2 = lds.ld(jz);
+                // A(kz) = (C(kz) + conj C(-kz)) / 2, B(kz) = (C(kz) - conj C(-kz)) / 2i
+                const float2 s1 = c_add(c1, c_conj(c2)), d1 = c_sub(c1, c_conj(c2));
+                const float2 A1 = c_scale(s1, 0.5f), B1 = make_float2(0.5f * d1.y, -0.5f * d1.x);
+                const float2 ya = c_mul(A1, z_operator<MODE>(a, o, 0, iy, iz));
+                const float2 yb = c_mul(B1, z_operator<MODE>(a, o, M, iy, iz));
+                lds.st(iz, make_float2(ya.x - yb.y, ya.y + yb.x));          // ya + i yb
+                if (jz != iz) {
+                    // A(-kz) = conj A(kz), B(-kz) = conj B(kz)
+                    const float2 za = c_mul(c_conj(A1), z_operator<MODE>(a, o, 0, iy, jz));
+                    const float2 zb = c_mul(c_conj(B1), z_operator<MODE>(a, o, M, iy, jz));
+                    lds.st(jz, make_float2(za.x - zb.y, za.y + zb.x));
+                }
+            }
         }
+        __syncthreads();
+        if (b == 0) {
+#pragma unroll
+            for (int m = 0; m < E; ++m)
+                if (m < cmid) v[m] = lds.ld(Eng::out_index(a.pf, t, m));
+        }
+        __syncthreads();
     }
     Eng::template run<true>(a.pi, a.t.tw_z, t, lds, v);
-    if (store) {
+    if (ok) {
         float2 *dst = pick3(a.out, o) + off;
 #pragma unroll
         for (int m = 0; m < E; ++m)
@@ -435,18 +508,21 @@ __global__ void __launch_bounds__(512) kw_xvel(XArgs a) {
 // Source values of the rows of this block, scattered into a per-row LDS line
 // of nx floats (zero where there is no source point).  Returns whether the
 // block has any source point (uniform over the block).
+// Only threads with `worker` set fill the line (one group per row); every
+// thread of the block takes the barriers.
 __device__ __forceinline__ bool scatter_source(const XArgs &a, float *line, int row, bool ok,
-                                               int t, int L, int b) {
+                                               int t, int L, int b, bool worker = true) {
     const int nx = a.g.nx;
     int beg = 0, end = 0;
-    if (a.src.row_ptr && ok) {
+    if (a.src.row_ptr && ok && worker) {
         beg = a.src.row_ptr[row];
         end = a.src.row_ptr[row + 1];
     }
     const bool any = __syncthreads_or(end > beg);
     if (!any) return false;
     float *mine = line + (size_t)b * nx;
-    for (int x = t; x < nx; x += L) mine[x] = 0.0f;
+    if (worker)
+        for (int x = t; x < nx; x += L) mine[x] = 0.0f;
     __syncthreads();
     for (int e = beg + t; e < end; e += L)
         mine[a.src.xpos[e]] = a.src.coef[e] * a.src.drive[a.src.elem[e]];
@@ -531,40 +607,63 @@ __device__ __forceinline__ void finish_pressure(const XArgs &a, float *line, int
     row_r2c<Eng>(a, a.Sout[0] + (size_t)(ok ? row : 0) * M, ok, t, lds, v);
 }
 
+// Density update.  The three split components are coupled only through
+// rho = sum rho_xi and sum du_xi, so a block runs them side by side: thread
+// group g (g = 0, 1, 2) transforms and updates component g of the block's tb
+// rows, the groups exchange the new rho_g and du_g through LDS, and then group
+// 0 transforms rho0 sum du, group 1 stores rho and transforms it (group 2 runs
+// the same barriers without storing).  Without absorption group 0 evaluates
+// the equation of state instead.  Each thread holds one component's values, as
+// in kw_xvel, instead of looping over the components with accumulators.
+// LDS: [3 exchange buffers][rho_g, du_g for 3 groups][source line per row]
 template <class Eng>
 __global__ void __launch_bounds__(512) kw_xden(XArgs a) {
-    KW_XPROLOGUE
+    constexpr int E = Eng::E;
+    extern __shared__ float2 sh[];
+    const int L = a.pf.L;
+    const int M = a.g.M, nx = a.g.nx, tb = a.tb;
+    const int tid = threadIdx.x;
+    const int g = tid / (tb * L);
+    const int rem = tid - g * tb * L;
+    const int b = rem / L, t = rem % L;
+    const int row = blockIdx.x * tb + b;
+    const bool ok = row < a.g.rows;
+    const int rr = ok ? row : 0;
     const int iy = rr % a.g.ny, iz = rr / a.g.ny;
-    float *line = reinterpret_cast<float *>(sh + (size_t)a.tb * row_pitch(M));
+    const size_t rbase = (size_t)rr * nx;
+    const int RP = row_pitch(M);
+    const RowLds lds{sh, (g * tb + b) * RP};
+    float2 *xch = sh + (size_t)3 * tb * RP;                 // [3][tb][M] rho_g, then [3][tb][M] du_g
+    float2 *rho_g = xch;
+    float2 *du_g = xch + (size_t)3 * tb * M;
+    float *line = reinterpret_cast<float *>(xch + (size_t)6 * tb * M);
     const float dt = a.g.dt;
-    const bool has_src = scatter_source(a, line, rr, ok, t, L, b);
+    const int cupd = Eng::out_count(a.pi, t);
+
+    const bool has_src = scatter_source(a, line, rr, ok, t, L, b, g == 0);
     const float *mysrc = line + (size_t)b * nx;
 
-    float2 acc_rho[E], acc_div[E];
-#pragma unroll
-    for (int m = 0; m < E; ++m) acc_rho[m] = acc_div[m] = make_float2(0.0f, 0.0f);
-
-#pragma unroll 1
-    for (int xi = 0; xi < 3; ++xi) {
-        const int salt = xi & a.zero;      // see kw_xvel
+    // phase 1: component g
+    {
         float2 v[E];
-        row_c2r<Eng>(a, pick3(a.Sin, xi) + (size_t)rr * M, ok, t, lds, v, salt);
-        if (ok) {
-            float *rho = pick3(a.fld, xi);
-            const float qy = a.t.pml_y[iy], qz = a.t.pml_z[iz];
+        row_c2r<Eng>(a, pick3(a.Sin, g) + (size_t)rr * M, ok, t, lds, v);
+        float *rho = pick3(a.fld, g);
+        const float qy = a.t.pml_y[iy], qz = a.t.pml_z[iz];
 #pragma unroll
-            for (int m = 0; m < E; ++m) {
-                if (m < cupd) {
-                    const int x = 2 * Eng::out_index(a.pi, t, m);
-                    const size_t i = rbase + x;
+        for (int m = 0; m < E; ++m) {
+            if (m < cupd) {
+                const int n = Eng::out_index(a.pi, t, m);
+                const int x = 2 * n;
+                const size_t i = rbase + x;
+                float2 nw = make_float2(0.0f, 0.0f);
+                const float2 d = v[m];
+                if (ok) {
                     float2 q;
-                    if (xi == 0) q = make_float2(a.t.pml_x[x + salt], a.t.pml_x[x + 1 + salt]);
-                    else if (xi == 1) q = make_float2(qy, qy);
+                    if (g == 0) q = make_float2(a.t.pml_x[x], a.t.pml_x[x + 1]);
+                    else if (g == 1) q = make_float2(qy, qy);
                     else q = make_float2(qz, qz);
                     const float2 r0 = coef2_at(a.m.rho0, i);
-                    const float2 d = v[m];
                     const float2 old = ld2(rho, i);
-                    float2 nw;
                     nw.x = q.x * (q.x * old.x - dt * r0.x * d.x);
                     nw.y = q.y * (q.y * old.y - dt * r0.y * d.y);
                     if (a.m.nonlinear) {
@@ -576,50 +675,50 @@ __global__ void __launch_bounds__(512) kw_xden(XArgs a) {
                         nw.y += mysrc[x + 1];
                     }
                     st2(rho, i, nw);
-                    acc_rho[m] = c_add(acc_rho[m], nw);
-                    acc_div[m] = c_add(acc_div[m], d);
                 }
+                rho_g[(size_t)(g * tb + b) * M + n] = nw;
+                du_g[(size_t)(g * tb + b) * M + n] = d;
             }
         }
     }
+    __syncthreads();
 
+    // phase 2: sums over the components, then the forward transforms
     float2 v[E];
-    if (a.m.absorbing) {
-        // store rho = sum rho_xi for the equation of state, transform rho0 sum du and rho
-        if (ok) {
 #pragma unroll
-            for (int m = 0; m < E; ++m) {
-                if (m < cupd) {
-                    const size_t i = rbase + 2 * Eng::out_index(a.pi, t, m);
-                    st2(a.rho_total, i, acc_rho[m]);
+    for (int m = 0; m < E; ++m) {
+        if (m < cupd) {
+            const int n = Eng::out_index(a.pi, t, m);
+            const size_t i = rbase + 2 * n;
+            const float2 r = c_add(c_add(rho_g[(size_t)b * M + n], rho_g[(size_t)(tb + b) * M + n]),
+                                   rho_g[(size_t)(2 * tb + b) * M + n]);
+            if (a.m.absorbing) {
+                if (g == 0) {
+                    const float2 s = c_add(c_add(du_g[(size_t)b * M + n], du_g[(size_t)(tb + b) * M + n]),
+                                           du_g[(size_t)(2 * tb + b) * M + n]);
                     const float2 r0 = coef2_at(a.m.rho0, i);
-                    v[m] = make_float2(r0.x * acc_div[m].x, r0.y * acc_div[m].y);
+                    v[m] = make_float2(r0.x * s.x, r0.y * s.y);
+                } else {
+                    v[m] = r;
+                    if (g == 1 && ok) st2(a.rho_total, i, r);
                 }
+            } else {
+                const float2 c2 = coef2_at(a.m.c0sq, i);
+                float2 pp = make_float2(c2.x * r.x, c2.y * r.y);
+                if (a.m.nonlinear) {
+                    const float2 nl = coef2_at(a.m.nl, i);
+                    pp.x += nl.x * r.x * r.x;
+                    pp.y += nl.y * r.y * r.y;
+                }
+                v[m] = pp;
             }
         }
-        row_r2c<Eng>(a, a.Sout[0] + (size_t)rr * M, ok, t, lds, v);
-#pragma unroll
-        for (int m = 0; m < E; ++m) v[m] = acc_rho[m];
-        row_r2c<Eng>(a, a.Sout[1] + (size_t)rr * M, ok, t, lds, v);
+    }
+    if (a.m.absorbing) {
+        float2 *dst = (g == 0) ? a.Sout[0] : a.Sout[1];
+        row_r2c<Eng>(a, dst + (size_t)rr * M, ok && g < 2, t, lds, v);
     } else {
-        if (ok) {
-#pragma unroll
-            for (int m = 0; m < E; ++m) {
-                if (m < cupd) {
-                    const size_t i = rbase + 2 * Eng::out_index(a.pi, t, m);
-                    const float2 rho = acc_rho[m];
-                    const float2 c2 = coef2_at(a.m.c0sq, i);
-                    float2 p = make_float2(c2.x * rho.x, c2.y * rho.y);
-                    if (a.m.nonlinear) {
-                        const float2 nl = coef2_at(a.m.nl, i);
-                        p.x += nl.x * rho.x * rho.x;
-                        p.y += nl.y * rho.y * rho.y;
-                    }
-                    v[m] = p;
-                }
-            }
-        }
-        finish_pressure<Eng>(a, line, rr, ok, t, L, b, lds, v);
+        finish_pressure<Eng>(a, line, rr, ok && g == 0, t, L, b, lds, v);
     }
 }
 

@@ -55,7 +55,11 @@ hipError_t launch_xden(hipStream_t s, const GridDev &g, const LaunchCfg &c, cons
     a.Sout[0] = Sout[0];
     a.Sout[1] = Sout[1];
     a.rho_total = rho_total;
-    KW_XLAUNCH(kw_xden, true);
+    a.tb = c.tb_den;
+    dim3 grid((g.rows + c.tb_den - 1) / c.tb_den);
+    dim3 block(3 * c.tb_den * c.px.L);
+    const size_t lds = den_lds_bytes(g.M, g.nx, c.tb_den);
+    KW_ENGINE_SWITCH(c.eng_x, hipLaunchKernelGGL((kw_xden<Eng>), grid, block, lds, s, a));
     return hipGetLastError();
 }
 

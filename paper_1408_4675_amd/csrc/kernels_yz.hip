@@ -57,23 +57,4 @@ hipError_t launch_zfused(hipStream_t s, const GridDev &g, const LaunchCfg &c, co
     return hipGetLastError();
 }
 
-hipError_t launch_zpair(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
-                        int mode, float2 *const *in, float2 *const *out) {
-    // one (ky, -ky) pair per block: the work is small and latency bound, so
-    // spread it over as many blocks as there are pairs
-    ZArgs a = make_zargs(g, c, t, mode, in, out);
-    a.tb = 2;
-    const int pairs_per_block = 1;
-    const int nout = (mode == ZM_ABS) ? 2 : 3;
-    dim3 grid((g.ny / 2 + 1 + pairs_per_block - 1) / pairs_per_block, nout);
-    dim3 block(a.tb * c.pz.L);
-    size_t lds = (size_t)2 * a.tb * g.nz * sizeof(float2);   // exchange + spectra
-    KW_ENGINE_SWITCH(c.eng_z, {
-        if (mode == ZM_GRAD) hipLaunchKernelGGL((kw_zpair<Eng, ZM_GRAD>), grid, block, lds, s, a);
-        else if (mode == ZM_DIV) hipLaunchKernelGGL((kw_zpair<Eng, ZM_DIV>), grid, block, lds, s, a);
-        else hipLaunchKernelGGL((kw_zpair<Eng, ZM_ABS>), grid, block, lds, s, a);
-    });
-    return hipGetLastError();
-}
-
 }  // namespace kw

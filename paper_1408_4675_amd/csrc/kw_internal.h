@@ -110,7 +110,7 @@ struct Counters {
 
 // kernel launch records -------------------------------------------------------
 enum KernelClass {
-    KC_YFWD = 0, KC_YINV, KC_ZGRAD, KC_ZDIV, KC_ZABS, KC_ZPAIR,
+    KC_YFWD = 0, KC_YINV, KC_ZGRAD, KC_ZDIV, KC_ZABS,
     KC_XVEL, KC_XDEN, KC_XEOS, KC_COUNT
 };
 
@@ -132,9 +132,17 @@ struct LaunchCfg {
     FftPlan py, pyi;         // y
     FftPlan pz, pzi;         // z
     int tb_x;                // rows per block in x kernels
+    int tb_den;              // rows per block of the density kernel (3 thread groups per row)
     int tb_y;                // columns per block in y kernels
     int tb_z;                // columns per block in z kernels
 };
+
+// LDS of the density kernel: 3 exchange buffers, rho_g and du_g of the 3
+// groups, and one source/sensor line per row
+inline size_t den_lds_bytes(int M, int nx, int tb) {
+    const size_t rp = (size_t)M + (M >> 4) + 1;
+    return (size_t)3 * tb * rp * 8 + (size_t)6 * tb * M * 8 + (size_t)tb * nx * 4;
+}
 
 // launchers (kernels_yz.hip, kernels_x.hip, kernels_util.hip) ---------------------
 hipError_t launch_ypass(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
@@ -142,9 +150,6 @@ hipError_t launch_ypass(hipStream_t s, const GridDev &g, const LaunchCfg &c, con
                         const Counters *prologue, const SourceDev *src);
 hipError_t launch_zfused(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
                          int mode, float2 *const *in, float2 *const *out);
-// column kx = 0 (packed kx = 0 / Nyquist) of the fused z pass
-hipError_t launch_zpair(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
-                        int mode, float2 *const *in, float2 *const *out);
 hipError_t launch_xvel(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
                        const Medium &m, float2 *const *S, float *const *u);
 hipError_t launch_xden(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
