@@ -13,7 +13,6 @@ The CPU baseline times the FP64 oracle on a bounded sample of the same 256^3
 workload on the host cores.
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -29,14 +28,6 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash():
-    h = hashlib.sha256()
-    for f in ("kernels.hip", "fft_dev.h", "kw_internal.h"):
-        with open(os.path.join(ROOT, "paper_1408_4675_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
 def measured_traffic(kernel_class, launches_bytes):
     """HBM bytes per launch of `kernel_class` from the committed rocprofv3 PMC
     summary, if it was taken on the current kernel sources; else None."""
@@ -45,6 +36,7 @@ def measured_traffic(kernel_class, launches_bytes):
         return None
     with open(path) as fh:
         d = json.load(fh)
+    from paper_1408_4675_amd.profiling import kernel_source_hash
     if d.get("source_hash") != kernel_source_hash():
         return None
     k = d.get("kernels", {}).get(kernel_class)

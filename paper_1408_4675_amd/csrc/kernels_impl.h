@@ -610,12 +610,14 @@ __device__ __forceinline__ void finish_pressure(const XArgs &a, float *line, int
 // Density update.  The three split components are coupled only through
 // rho = sum rho_xi and sum du_xi, so a block runs them side by side: thread
 // group g (g = 0, 1, 2) transforms and updates component g of the block's tb
-// rows, the groups exchange the new rho_g and du_g through LDS, and then group
-// 0 transforms rho0 sum du, group 1 stores rho and transforms it (group 2 runs
-// the same barriers without storing).  Without absorption group 0 evaluates
-// the equation of state instead.  Each thread holds one component's values, as
-// in kw_xvel, instead of looping over the components with accumulators.
-// LDS: [3 exchange buffers][rho_g, du_g for 3 groups][source line per row]
+// rows, and then group 0 transforms rho0 sum du and group 1 stores rho and
+// transforms it (group 2 takes the same barriers without storing).  Without
+// absorption group 1 evaluates the equation of state instead.  Each thread
+// holds one component's values, as in kw_xvel.
+// The groups exchange only what the others need: group 0 keeps du_0 and group
+// 1 keeps rho_1 in registers; rho_0, du_1 and rho_2 go to the (then idle) FFT
+// buffers of groups 0, 1 and 2, and du_2 to a line of its own.
+// LDS: [3 groups][tb rows] FFT buffers, [tb] du_2 lines, [tb] source lines.
 template <class Eng>
 __global__ void __launch_bounds__(512) kw_xden(XArgs a) {
     constexpr int E = Eng::E;
@@ -633,22 +635,25 @@ __global__ void __launch_bounds__(512) kw_xden(XArgs a) {
     const size_t rbase = (size_t)rr * nx;
     const int RP = row_pitch(M);
     const RowLds lds{sh, (g * tb + b) * RP};
-    float2 *xch = sh + (size_t)3 * tb * RP;                 // [3][tb][M] rho_g, then [3][tb][M] du_g
-    float2 *rho_g = xch;
-    float2 *du_g = xch + (size_t)3 * tb * M;
-    float *line = reinterpret_cast<float *>(xch + (size_t)6 * tb * M);
+    float2 *buf0 = sh + (size_t)b * RP;                      // row b's buffer of group 0
+    float2 *buf1 = sh + (size_t)(tb + b) * RP;
+    float2 *buf2 = sh + (size_t)(2 * tb + b) * RP;
+    float2 *du2 = sh + (size_t)3 * tb * RP + (size_t)b * M;   // nx floats per row
+    float *line = reinterpret_cast<float *>(sh + (size_t)3 * tb * RP + (size_t)tb * M);
     const float dt = a.g.dt;
     const int cupd = Eng::out_count(a.pi, t);
 
     const bool has_src = scatter_source(a, line, rr, ok, t, L, b, g == 0);
     const float *mysrc = line + (size_t)b * nx;
 
-    // phase 1: component g
+    // phase 1: component g (row_c2r ends with a barrier, so the FFT buffers
+    // are free for the exchange afterwards)
+    float2 v[E];
+    row_c2r<Eng>(a, pick3(a.Sin, g) + (size_t)rr * M, ok, t, lds, v);
     {
-        float2 v[E];
-        row_c2r<Eng>(a, pick3(a.Sin, g) + (size_t)rr * M, ok, t, lds, v);
         float *rho = pick3(a.fld, g);
         const float qy = a.t.pml_y[iy], qz = a.t.pml_z[iz];
+        float2 *xrho = (g == 0) ? buf0 : buf2;
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             if (m < cupd) {
@@ -676,49 +681,54 @@ __global__ void __launch_bounds__(512) kw_xden(XArgs a) {
                     }
                     st2(rho, i, nw);
                 }
-                rho_g[(size_t)(g * tb + b) * M + n] = nw;
-                du_g[(size_t)(g * tb + b) * M + n] = d;
+                if (g == 1) {
+                    buf1[n] = d;
+                    v[m] = nw;
+                } else {
+                    xrho[n] = nw;
+                    if (g == 2) du2[n] = d;
+                }
             }
         }
     }
     __syncthreads();
 
-    // phase 2: sums over the components, then the forward transforms
-    float2 v[E];
+    // phase 2: sums over the components (group 0: sum du, group 1: rho)
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         if (m < cupd) {
             const int n = Eng::out_index(a.pi, t, m);
             const size_t i = rbase + 2 * n;
-            const float2 r = c_add(c_add(rho_g[(size_t)b * M + n], rho_g[(size_t)(tb + b) * M + n]),
-                                   rho_g[(size_t)(2 * tb + b) * M + n]);
-            if (a.m.absorbing) {
-                if (g == 0) {
-                    const float2 s = c_add(c_add(du_g[(size_t)b * M + n], du_g[(size_t)(tb + b) * M + n]),
-                                           du_g[(size_t)(2 * tb + b) * M + n]);
+            if (g == 0) {
+                if (a.m.absorbing) {
+                    const float2 s = c_add(c_add(v[m], buf1[n]), du2[n]);
                     const float2 r0 = coef2_at(a.m.rho0, i);
                     v[m] = make_float2(r0.x * s.x, r0.y * s.y);
-                } else {
+                }
+            } else if (g == 1) {
+                const float2 r = c_add(c_add(v[m], buf0[n]), buf2[n]);
+                if (a.m.absorbing) {
                     v[m] = r;
-                    if (g == 1 && ok) st2(a.rho_total, i, r);
+                    if (ok) st2(a.rho_total, i, r);
+                } else {
+                    const float2 c2 = coef2_at(a.m.c0sq, i);
+                    float2 pp = make_float2(c2.x * r.x, c2.y * r.y);
+                    if (a.m.nonlinear) {
+                        const float2 nl = coef2_at(a.m.nl, i);
+                        pp.x += nl.x * r.x * r.x;
+                        pp.y += nl.y * r.y * r.y;
+                    }
+                    v[m] = pp;
                 }
-            } else {
-                const float2 c2 = coef2_at(a.m.c0sq, i);
-                float2 pp = make_float2(c2.x * r.x, c2.y * r.y);
-                if (a.m.nonlinear) {
-                    const float2 nl = coef2_at(a.m.nl, i);
-                    pp.x += nl.x * r.x * r.x;
-                    pp.y += nl.y * r.y * r.y;
-                }
-                v[m] = pp;
             }
         }
     }
+    __syncthreads();   // the forward transforms below overwrite the exchanged values
     if (a.m.absorbing) {
         float2 *dst = (g == 0) ? a.Sout[0] : a.Sout[1];
         row_r2c<Eng>(a, dst + (size_t)rr * M, ok && g < 2, t, lds, v);
     } else {
-        finish_pressure<Eng>(a, line, rr, ok && g == 0, t, L, b, lds, v);
+        finish_pressure<Eng>(a, line, rr, ok && g == 1, t, L, b, lds, v);
     }
 }
 

@@ -137,11 +137,11 @@ struct LaunchCfg {
     int tb_z;                // columns per block in z kernels
 };
 
-// LDS of the density kernel: 3 exchange buffers, rho_g and du_g of the 3
-// groups, and one source/sensor line per row
+// LDS of the density kernel: the FFT buffers of its 3 thread groups, and two
+// lines of nx floats per row (du of component z; source / sensor values)
 inline size_t den_lds_bytes(int M, int nx, int tb) {
     const size_t rp = (size_t)M + (M >> 4) + 1;
-    return (size_t)3 * tb * rp * 8 + (size_t)6 * tb * M * 8 + (size_t)tb * nx * 4;
+    return (size_t)3 * tb * rp * 8 + (size_t)tb * M * 8 + (size_t)tb * nx * 4;
 }
 
 // launchers (kernels_yz.hip, kernels_x.hip, kernels_util.hip) ---------------------

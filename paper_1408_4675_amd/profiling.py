@@ -1,0 +1,211 @@
+"""Summaries of rocprofv3 runs of this library, and a plain copy kernel that
+calibrates the HBM traffic counters.
+
+    python -m paper_1408_4675_amd.profiling copy [--mib N] [--reps K]
+        a device-to-device copy of N MiB, K times (the reference kernel whose
+        FETCH_SIZE / WRITE_SIZE give bytes-per-KiB scale factors)
+    python -m paper_1408_4675_amd.profiling stats DIR --out FILE.md --title T --command C
+        turn the kernel_stats.csv that `rocprofv3 --kernel-trace --stats
+        --output-format csv` wrote under DIR into a short Markdown table
+    python -m paper_1408_4675_amd.profiling traffic --fetch DIR --write DIR
+            --copy-fetch DIR --copy-write DIR --copy-mib N --out FILE.json --command C
+        mean FETCH_SIZE and WRITE_SIZE per dispatch of every kernel class,
+        scaled by what the counters read for the copy kernel, as JSON with the
+        hash of the kernel sources they were taken on
+
+Nothing here computes any part of the solver.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+from typing import Dict, List, Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+
+# kernel name fragment -> class name reported by kw_stats
+CLASS_OF = (("kw_ypass", None), ("kw_zfused", None), ("kw_xvel", "xvel"), ("kw_xden", "xden"),
+            ("kw_xeos", "xeos"), ("kw_xfwd", "xfwd"), ("kw_xinv", "xinv"),
+            ("kw_finalize", "finalize"), ("kw_fill", "fill"))
+
+
+def kernel_source_hash() -> str:
+    """Hash of every kernel source file; a traffic table is valid only for
+    the sources it was measured on."""
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(CSRC)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(CSRC, f), "rb") as fh:
+                h.update(f.encode())
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def kernel_class(name: str) -> Optional[str]:
+    """Class of a demangled kernel name (None for kernels of other code)."""
+    if "kw_ypass" in name:
+        return "ypass_inv" if "true>" in name else "ypass_fwd"
+    if "kw_zfused" in name:
+        for mode, cls in ((", 0>", "zfused_grad"), (", 1>", "zfused_div"), (", 2>", "zfused_abs")):
+            if mode in name:
+                return cls
+        return "zfused"
+    for frag, cls in CLASS_OF:
+        if cls and frag in name:
+            return cls
+    if "copy" in name.lower() or "elementwise" in name.lower():
+        return "copy"
+    return None
+
+
+def _find(d: str, suffix: str) -> str:
+    hits = sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
+    if not hits:
+        raise FileNotFoundError("no *%s under %s" % (suffix, d))
+    return hits[-1]
+
+
+def _col(row: Dict[str, str], *names: str) -> str:
+    for n in names:
+        if n in row:
+            return row[n]
+    raise KeyError("none of %s in %s" % (names, list(row)))
+
+
+def read_kernel_stats(d: str) -> List[Dict]:
+    with open(_find(d, "kernel_stats.csv")) as fh:
+        rows = list(csv.DictReader(fh))
+    out = []
+    for r in rows:
+        out.append(dict(name=_col(r, "Name", "KernelName", "Kernel_Name"),
+                        calls=int(_col(r, "Calls")),
+                        total_ns=float(_col(r, "TotalDurationNs", "Total_Duration_ns")),
+                        avg_ns=float(_col(r, "AverageNs", "Average_ns")),
+                        pct=float(_col(r, "Percentage"))))
+    out.sort(key=lambda r: -r["total_ns"])
+    return out
+
+
+def stats_markdown(d: str, title: str, command: str) -> str:
+    rows = read_kernel_stats(d)
+    lines = ["# %s" % title, "", "Command (from the repository root, on one MI355X; "
+             "R is the repository root):", "", "    " + command, "",
+             "Durations in microseconds, from rocprofv3 kernel_stats.csv.", "",
+             "| kernel | class | calls | total us | average us | % |", "|---|---|---|---|---|---|"]
+    for r in rows:
+        lines.append("| %s | %s | %d | %.1f | %.2f | %.1f |" % (
+            r["name"].replace("|", "/"), kernel_class(r["name"]) or "-", r["calls"],
+            r["total_ns"] / 1e3, r["avg_ns"] / 1e3, r["pct"]))
+    per = {}
+    for r in rows:
+        c = kernel_class(r["name"])
+        if c:
+            e = per.setdefault(c, [0, 0.0])
+            e[0] += r["calls"]
+            e[1] += r["total_ns"]
+    lines += ["", "Per class (average launch duration, us):", "",
+              "| class | launches | average us |", "|---|---|---|"]
+    for c, (n, ns) in sorted(per.items(), key=lambda kv: -kv[1][1]):
+        lines.append("| %s | %d | %.2f |" % (c, n, ns / n / 1e3))
+    return "\n".join(lines) + "\n"
+
+
+def read_counter(d: str, counter: str) -> Dict[str, List[float]]:
+    """Per kernel class, the list of `counter` values (one per dispatch)."""
+    with open(_find(d, "counter_collection.csv")) as fh:
+        rows = list(csv.DictReader(fh))
+    per: Dict[str, Dict[str, float]] = {}
+    for r in rows:
+        if _col(r, "Counter_Name", "Counter-Name") != counter:
+            continue
+        name = _col(r, "Kernel_Name", "Kernel-Name", "KernelName")
+        disp = _col(r, "Dispatch_Id", "Dispatch-Id", "Correlation_Id")
+        c = kernel_class(name)
+        if c is None:
+            continue
+        # one row per dispatch (and per dimension instance: summed)
+        per.setdefault(c, {}).setdefault(disp, 0.0)
+        per[c][disp] += float(_col(r, "Counter_Value", "Counter-Value"))
+    return {c: list(v.values()) for c, v in per.items()}
+
+
+def _mean(x: List[float]) -> float:
+    return sum(x) / len(x)
+
+
+def traffic_table(fetch: str, write: str, copy_fetch: str, copy_write: str,
+                  copy_mib: float) -> Dict:
+    copy_bytes = copy_mib * 2 ** 20
+    cf = read_counter(copy_fetch, "FETCH_SIZE")["copy"]
+    cw = read_counter(copy_write, "WRITE_SIZE")["copy"]
+    # the largest dispatches are the calibration copies (smaller ones are set-up)
+    f_kib = max(cf)
+    w_kib = max(cw)
+    f_scale = copy_bytes / f_kib        # bytes per counter KiB
+    w_scale = copy_bytes / w_kib
+    kf = read_counter(fetch, "FETCH_SIZE")
+    kw = read_counter(write, "WRITE_SIZE")
+    kernels = {}
+    for c in sorted(set(kf) & set(kw)):
+        if c == "copy":
+            continue
+        fb = _mean(kf[c]) * f_scale
+        wb = _mean(kw[c]) * w_scale
+        kernels[c] = dict(fetch_bytes_per_launch=fb, write_bytes_per_launch=wb,
+                          hbm_bytes_per_launch=fb + wb, dispatches=len(kf[c]))
+    return dict(source_hash=kernel_source_hash(), copy_mib=copy_mib,
+                copy_fetch_kib=f_kib, copy_write_kib=w_kib,
+                fetch_scale_bytes_per_kib=f_scale, write_scale_bytes_per_kib=w_scale,
+                kernels=kernels)
+
+
+def copy_probe(mib: int, reps: int):
+    import torch
+    n = mib * 2 ** 20 // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print("copied %d MiB %d times" % (mib, reps), flush=True)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(prog="python -m paper_1408_4675_amd.profiling")
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    p = sub.add_parser("copy")
+    p.add_argument("--mib", type=int, default=1024)
+    p.add_argument("--reps", type=int, default=5)
+    p = sub.add_parser("stats")
+    p.add_argument("dir")
+    p.add_argument("--out", required=True)
+    p.add_argument("--title", required=True)
+    p.add_argument("--command", required=True)
+    p = sub.add_parser("traffic")
+    for k in ("fetch", "write", "copy-fetch", "copy-write", "out", "command"):
+        p.add_argument("--" + k, required=True)
+    p.add_argument("--copy-mib", type=float, default=1024)
+    a = ap.parse_args(argv)
+    if a.cmd == "copy":
+        copy_probe(a.mib, a.reps)
+    elif a.cmd == "stats":
+        with open(a.out, "w") as fh:
+            fh.write(stats_markdown(a.dir, a.title, a.command))
+        print("wrote", a.out)
+    else:
+        d = traffic_table(a.fetch, a.write, a.copy_fetch, a.copy_write, a.copy_mib)
+        d["command"] = a.command
+        with open(a.out, "w") as fh:
+            json.dump(d, fh, indent=1, sort_keys=True)
+        print(json.dumps(d["kernels"], indent=1))
+
+
+if __name__ == "__main__":
+    sys.exit(main())
