@@ -612,10 +612,20 @@ int pick_tiles(kw_sim *s, int tile_y, int tile_z) {
         return (size_t)tb * (g.M + (g.M >> 4) + 1) * sizeof(float2) + (size_t)tb * g.nx * sizeof(float);
     };
     while (c.tb_x > 1 && x_lds_bytes(c.tb_x) > 64 * 1024) c.tb_x /= 2;
-    c.tb_den = std::max(1, 512 / (3 * c.px.L));
-    while (c.tb_den > 1 && den_lds_bytes(g.M, g.nx, c.tb_den) > 64 * 1024) --c.tb_den;
-    if (3 * c.px.L > 512 || den_lds_bytes(g.M, g.nx, c.tb_den) > 64 * 1024)
-        return fail(KW_EUNSUPPORTED, "density pass does not fit a block (nx = %d)", g.nx);
+    // rows per block of the density kernel: as many as fit 512 threads and
+    // 64 KB of LDS (measured: two blocks of ~8 wavefronts per CU beat smaller
+    // blocks, and thread groups that straddle wavefronts cost little)
+    {
+        const bool line = den_needs_line(s->med, s->src, s->sen);
+        auto fits = [&](int tb) {
+            return 3 * tb * c.px.L <= 512 && den_lds_bytes(g.M, g.nx, tb, line) <= 64 * 1024;
+        };
+        int best = 0;
+        for (int tb = 1; fits(tb); ++tb) best = tb;
+        if (best == 0)
+            return fail(KW_EUNSUPPORTED, "density pass does not fit a block (nx = %d)", g.nx);
+        c.tb_den = best;
+    }
     auto col_tile = [&](int n, int L, int req) {
         if (req > 0) return req;
         int tb = 16;
@@ -732,10 +742,6 @@ int kw_create(const kw_grid *grid, const kw_medium *medium, const kw_source *sou
     g.dt = (float)dt;
     g.y_tau = (float)((y - 2.0) / 2.0);
     g.y_eta = (float)((y - 1.0) / 2.0);
-    if ((rc = pick_tiles(s, 0, 0)) != KW_OK) {
-        delete s;
-        return rc;
-    }
 
     std::vector<std::pair<size_t, std::vector<char>>> up;   // (offset, bytes)
     auto put = [&](size_t off, const void *p, size_t n) {
@@ -957,6 +963,12 @@ int kw_create(const kw_grid *grid, const kw_medium *medium, const kw_source *sou
     }
     s->buf.rho_total = L.rho_total ? s->at<float>(L.rho_total) : nullptr;
     for (int i = 0; i < 7; ++i) s->buf.S[i] = s->at<float2>(L.S[i]);
+
+    // launch shapes (they depend on the source and sensor set-up above)
+    if ((rc = pick_tiles(s, 0, 0)) != KW_OK) {
+        delete s;
+        return rc;
+    }
 
     // device work: uploads, then zero the state
     auto bail = [&](int code) {

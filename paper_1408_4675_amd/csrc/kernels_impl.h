@@ -282,14 +282,26 @@ __global__ void __launch_bounds__(512) kw_zfused(ZArgs a) {
     const int ny = a.g.ny, M = a.g.M;
     const size_t stride = (size_t)M * ny;
     const ColLds lds{sh, a.tb, b};
-    const int blk = blockIdx.x;
     const int cin = Eng::in_count(a.pf, t);
     const int cmid = Eng::out_count(a.pf, t);
     const int cout = Eng::out_count(a.pi, t);
-    // blockIdx.y selects the output; each output has its own blocks (the
-    // gradient's three outputs re-read the one input), which keeps a block to
-    // one forward and one inverse transform and its register use low
-    const int o = blockIdx.y;
+    // Each output has its own blocks, which keeps a block to one forward and
+    // one inverse transform and its register use low.  The divergence and
+    // absorption outputs read inputs of their own (blockIdx.y = output).  The
+    // gradient's three outputs read the same input tile: its blocks come in
+    // a 1D grid ordered so that the three blocks of a tile land on the same
+    // XCD (workgroups go round-robin over the 8 XCDs) one after another, and
+    // the second and third reads of the tile hit that XCD's L2.
+    int blk, o;
+    if constexpr (MODE == ZM_GRAD) {
+        const int B = blockIdx.x, q = B >> 3;
+        blk = (q / 3) * 8 + (B & 7);
+        o = q % 3;
+        if (blk >= a.ntiles * a.g.ny) return;          // whole block: padding of the grid
+    } else {
+        blk = blockIdx.x;
+        o = blockIdx.y;
+    }
     const int f = (MODE == ZM_GRAD) ? 0 : o;
 
     const int tile = blk % a.ntiles, iy = blk / a.ntiles;
@@ -570,7 +582,7 @@ __device__ __forceinline__ void record_mask(const XArgs &a, float *line, int row
 
 // sensors, non-finite check and x r2c of the new pressure (v holds p in the
 // output layout of the inverse x transform)
-template <class Eng>
+template <class Eng, bool MASK = true>
 __device__ __forceinline__ void finish_pressure(const XArgs &a, float *line, int row, bool ok,
                                                 int t, int L, int b, const RowLds &lds,
                                                 float2 (&v)[Eng::E]) {
@@ -602,8 +614,10 @@ __device__ __forceinline__ void finish_pressure(const XArgs &a, float *line, int
         }
     }
     if (bad) atomicMin(a.cnt.nonfinite, step);
-    if (rec && !a.sen.all_points && a.sen.row_ptr)
-        record_mask<Eng>(a, line, row, ok, t, L, b, step, v);
+    if constexpr (MASK) {
+        if (rec && !a.sen.all_points && a.sen.row_ptr)
+            record_mask<Eng>(a, line, row, ok, t, L, b, step, v);
+    }
     row_r2c<Eng>(a, a.Sout[0] + (size_t)(ok ? row : 0) * M, ok, t, lds, v);
 }
 
@@ -618,7 +632,10 @@ __device__ __forceinline__ void finish_pressure(const XArgs &a, float *line, int
 // 1 keeps rho_1 in registers; rho_0, du_1 and rho_2 go to the (then idle) FFT
 // buffers of groups 0, 1 and 2, and du_2 to a line of its own.
 // LDS: [3 groups][tb rows] FFT buffers, [tb] du_2 lines, [tb] source lines.
-template <class Eng>
+// ABS (= a.m.absorbing) is a template parameter: the lossless tail (equation
+// of state, sensors, pressure transform) would otherwise set the register
+// count of the absorbing kernel too.
+template <class Eng, bool ABS>
 __global__ void __launch_bounds__(512) kw_xden(XArgs a) {
     constexpr int E = Eng::E;
     extern __shared__ float2 sh[];
@@ -700,14 +717,14 @@ __global__ void __launch_bounds__(512) kw_xden(XArgs a) {
             const int n = Eng::out_index(a.pi, t, m);
             const size_t i = rbase + 2 * n;
             if (g == 0) {
-                if (a.m.absorbing) {
+                if constexpr (ABS) {
                     const float2 s = c_add(c_add(v[m], buf1[n]), du2[n]);
                     const float2 r0 = coef2_at(a.m.rho0, i);
                     v[m] = make_float2(r0.x * s.x, r0.y * s.y);
                 }
             } else if (g == 1) {
                 const float2 r = c_add(c_add(v[m], buf0[n]), buf2[n]);
-                if (a.m.absorbing) {
+                if constexpr (ABS) {
                     v[m] = r;
                     if (ok) st2(a.rho_total, i, r);
                 } else {
@@ -724,7 +741,7 @@ __global__ void __launch_bounds__(512) kw_xden(XArgs a) {
         }
     }
     __syncthreads();   // the forward transforms below overwrite the exchanged values
-    if (a.m.absorbing) {
+    if constexpr (ABS) {
         float2 *dst = (g == 0) ? a.Sout[0] : a.Sout[1];
         row_r2c<Eng>(a, dst + (size_t)rr * M, ok && g < 2, t, lds, v);
     } else {
@@ -732,7 +749,9 @@ __global__ void __launch_bounds__(512) kw_xden(XArgs a) {
     }
 }
 
-template <class Eng>
+// MASK: mask sensors are recorded (their row scan is compiled in only then,
+// which keeps the register count of the all-points and no-sensor cases lower)
+template <class Eng, bool MASK>
 __global__ void __launch_bounds__(512) kw_xeos(XArgs a) {
     KW_XPROLOGUE
     float *line = reinterpret_cast<float *>(sh + (size_t)a.tb * row_pitch(M));
@@ -760,7 +779,7 @@ __global__ void __launch_bounds__(512) kw_xeos(XArgs a) {
             }
         }
     }
-    finish_pressure<Eng>(a, line, rr, ok, t, L, b, lds, v);
+    finish_pressure<Eng, MASK>(a, line, rr, ok, t, L, b, lds, v);
 }
 
 template <class Eng>

@@ -58,8 +58,12 @@ hipError_t launch_xden(hipStream_t s, const GridDev &g, const LaunchCfg &c, cons
     a.tb = c.tb_den;
     dim3 grid((g.rows + c.tb_den - 1) / c.tb_den);
     dim3 block(3 * c.tb_den * c.px.L);
-    const size_t lds = den_lds_bytes(g.M, g.nx, c.tb_den);
-    KW_ENGINE_SWITCH(c.eng_x, hipLaunchKernelGGL((kw_xden<Eng>), grid, block, lds, s, a));
+    const size_t lds = den_lds_bytes(g.M, g.nx, c.tb_den, den_needs_line(m, src, sen));
+    if (m.absorbing) {
+        KW_ENGINE_SWITCH(c.eng_x, hipLaunchKernelGGL((kw_xden<Eng, true>), grid, block, lds, s, a));
+    } else {
+        KW_ENGINE_SWITCH(c.eng_x, hipLaunchKernelGGL((kw_xden<Eng, false>), grid, block, lds, s, a));
+    }
     return hipGetLastError();
 }
 
@@ -74,7 +78,16 @@ hipError_t launch_xeos(hipStream_t s, const GridDev &g, const LaunchCfg &c, cons
     a.Sin[1] = Sin[1];
     a.rho_total = const_cast<float *>(rho_total);
     a.Sout[0] = Sout;
-    KW_XLAUNCH(kw_xeos, true);
+    // the per-row line is only needed to pick mask sensor points out of a row
+    const bool mask = sen.row_ptr != nullptr && !sen.all_points;
+    dim3 grid((g.rows + c.tb_x - 1) / c.tb_x);
+    dim3 block(c.tb_x * c.px.L);
+    const size_t lds = x_lds(g, c, mask);
+    if (mask) {
+        KW_ENGINE_SWITCH(c.eng_x, hipLaunchKernelGGL((kw_xeos<Eng, true>), grid, block, lds, s, a));
+    } else {
+        KW_ENGINE_SWITCH(c.eng_x, hipLaunchKernelGGL((kw_xeos<Eng, false>), grid, block, lds, s, a));
+    }
     return hipGetLastError();
 }
 

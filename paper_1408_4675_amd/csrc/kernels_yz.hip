@@ -46,7 +46,9 @@ hipError_t launch_zfused(hipStream_t s, const GridDev &g, const LaunchCfg &c, co
                          int mode, float2 *const *in, float2 *const *out) {
     const ZArgs a = make_zargs(g, c, t, mode, in, out);
     const int nout = (mode == ZM_ABS) ? 2 : 3;
-    dim3 grid(a.ntiles * g.ny, nout);
+    const int nblk = a.ntiles * g.ny;
+    // gradient: 1D grid, XCD-aware order (see kw_zfused), padded to whole groups of 8 tiles
+    dim3 grid = (mode == ZM_GRAD) ? dim3((nblk + 7) / 8 * 8 * 3, 1) : dim3(nblk, nout);
     dim3 block(a.tb * c.pz.L);
     size_t lds = (size_t)a.tb * g.nz * sizeof(float2);
     KW_ENGINE_SWITCH(c.eng_z, {

@@ -137,11 +137,15 @@ struct LaunchCfg {
     int tb_z;                // columns per block in z kernels
 };
 
-// LDS of the density kernel: the FFT buffers of its 3 thread groups, and two
-// lines of nx floats per row (du of component z; source / sensor values)
-inline size_t den_lds_bytes(int M, int nx, int tb) {
+// LDS of the density kernel: the FFT buffers of its 3 thread groups, a line
+// of nx floats per row for du of component z, and, when `line`, one more for
+// source values (or mask sensor values in the lossless case)
+inline bool den_needs_line(const Medium &m, const SourceDev &src, const SensorDev &sen) {
+    return src.row_ptr != nullptr || (!m.absorbing && sen.row_ptr != nullptr && !sen.all_points);
+}
+inline size_t den_lds_bytes(int M, int nx, int tb, bool line) {
     const size_t rp = (size_t)M + (M >> 4) + 1;
-    return (size_t)3 * tb * rp * 8 + (size_t)tb * M * 8 + (size_t)tb * nx * 4;
+    return (size_t)3 * tb * rp * 8 + (size_t)tb * M * 8 + (line ? (size_t)tb * nx * 4 : 0);
 }
 
 // launchers (kernels_yz.hip, kernels_x.hip, kernels_util.hip) ---------------------
