@@ -18,6 +18,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -99,6 +101,37 @@ def pass_model_bytes(stats):
     return tot_b
 
 
+def copy_ceiling(mib=1024, reps=10):
+    """Device-to-device copy bandwidth (read + write bytes / time): the
+    practical HBM ceiling the kernels are compared against."""
+    import torch
+    n = mib * 2 ** 20 // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    gbs = 2 * n * 4 * reps / dt / 1e9
+    del a, b
+    return round(gbs, 1)
+
+
+def host_info():
+    mem_gb = None
+    try:
+        with open("/proc/meminfo") as fh:
+            for line in fh:
+                if line.startswith("MemTotal:"):
+                    mem_gb = round(int(line.split()[1]) / 2 ** 20, 1)
+    except OSError:
+        pass
+    return dict(nproc=os.cpu_count(), ram_gib=mem_gb)
+
+
 def cpu_baseline(scen, warm=1, steps=2):
     import numpy as np
     from oracle import Oracle
@@ -110,7 +143,39 @@ def cpu_baseline(scen, warm=1, steps=2):
     return dict(value=round(scen.grid.npts * steps / dt, 1), unit="grid-point updates/s",
                 cores=o.workers, kind="oracle",
                 sample="FP64 NumPy/SciPy oracle, %d timed steps (after %d warm-up) of the same "
-                       "256^3 tissue workload; %.1f s" % (steps, warm, dt))
+                       "256^3 tissue workload; %.1f s" % (steps, warm, dt),
+                host=host_info())
+
+
+def serving_bench(n_requests, rate=20.0, seed=0):
+    """Continuous batching vs one-at-a-time FIFO on the same Poisson trace,
+    then both again at a sustainable rate (70 % of the measured batched
+    capacity)."""
+    from paper_1408_4675_amd import scenarios as sc
+    from paper_1408_4675_amd.serving import Server, run_fifo, summarize
+    log("building the serving trace (%d requests, %.0f/s)" % (n_requests, rate))
+    reqs = sc.serving_trace(seed=seed, n_requests=n_requests, rate=rate, medium_pool=2)
+    out = dict(metric="serving latency and throughput (Poisson trace, 64^3-256^3 tissue)",
+               trace=dict(requests=n_requests, rate_per_s=rate, seed=seed,
+                          sizes=list(sc.SERVING_SIZES), steps="300-1500",
+                          offered_point_updates_per_s=rate * float(np.mean(
+                              [r.scenario.grid.npts * r.scenario.steps for r in reqs]))))
+    log("batched")
+    srv = Server(max_active=8, chunk_steps=64)
+    out["batched"] = summarize(srv.run(reqs, on_done=lambda r: log("done %d" % r.rid)))
+    out["batched"]["peak_active"] = srv.peak_active
+    log("fifo")
+    out["fifo"] = summarize(run_fifo(reqs))
+    cap = out["batched"]["point_updates_per_s"]
+    work = float(np.mean([r.scenario.grid.npts * r.scenario.steps for r in reqs]))
+    lam = 0.7 * cap / work
+    log("sustainable rate %.2f/s" % lam)
+    reqs2 = sc.serving_trace(seed=seed, n_requests=n_requests, rate=lam, medium_pool=2)
+    out["sustainable_rate_per_s"] = lam
+    srv2 = Server(max_active=8, chunk_steps=64)
+    out["batched_at_sustainable"] = summarize(srv2.run(reqs2))
+    out["fifo_at_sustainable"] = summarize(run_fifo(reqs2))
+    return out
 
 
 def main():
@@ -121,6 +186,9 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the 1024^3 item")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--large-steps", type=int, default=100)
+    ap.add_argument("--serving", type=int, default=0, metavar="N",
+                    help="instead of the step benchmark, serve the first N requests of the "
+                         "Poisson trace (20/s, 64^3-256^3 tissue) batched and one at a time")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -132,6 +200,10 @@ def main():
     from paper_1408_4675_amd import _abi
     _abi.load()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+    if args.serving:
+        print(json.dumps(serving_bench(args.serving)), flush=True)
+        return
 
     log("building 256^3 tissue workload")
     scen = sc.tissue_bowl(seed=0, n=256, steps=args.steps)
@@ -155,9 +227,16 @@ def main():
         roofline=roof,
         step_roofline=dict(pass_model_bytes_per_point=round(step_bytes / npts, 2),
                            achieved_gbs=round(step_bytes / (ms_per_step / 1e3) / 1e9, 1),
-                           frac=round(step_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4)),
+                           frac=round(step_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                           # state u, rho r/w (48 B) + 4 medium maps (16 B) + 2 sensor
+                           # accumulators r/w (16 B): what any scheme must move per step
+                           compulsory_bytes_per_point=80,
+                           compulsory_frac=round(80.0 * npts / (ms_per_step / 1e3) / 1e9
+                                                 / HBM_PEAK_GBS, 4)),
         per_class=per_class,
     )
+    log("measuring the device copy ceiling")
+    out["copy_ceiling_gbs"] = copy_ceiling()
     if not args.no_large:
         try:
             log("building 1024^3 water workload")

@@ -190,6 +190,20 @@ int kw_set_graph(kw_sim *sim, int32_t steps_per_graph);
 int kw_set_plan(kw_sim *sim, int axis, const int32_t *radices, int32_t n_radices,
                 int32_t tile);
 
+/* State snapshots (checkpoint / restart, Section 3.4: a run can be stopped
+ * and resumed from its saved state).  A snapshot holds the step counter, the
+ * non-finite flag, u_x, u_y, u_z, rho_x, rho_y, rho_z, the pressure (as its
+ * packed spectrum) and the sensor accumulators, behind a header that records
+ * the set-up it belongs to.  kw_state_bytes gives its size (-1 for NULL).
+ * kw_save writes it to dst (device memory when dst_is_device != 0, else host
+ * memory); kw_load restores it into a simulation created with the same grid,
+ * medium flags, time step and sensor set-up (KW_EINVAL otherwise, before
+ * anything is overwritten).  Continuing after kw_load gives bit-for-bit the
+ * results of the run that was saved.  Both calls synchronize the stream. */
+int64_t kw_state_bytes(kw_sim *sim);
+int kw_save(kw_sim *sim, void *dst, size_t dst_bytes, int dst_is_device);
+int kw_load(kw_sim *sim, const void *src, size_t src_bytes, int src_is_device);
+
 /* Free library-owned host state (never the workspace).  NULL-safe. */
 int kw_destroy(kw_sim *sim);
 

@@ -39,7 +39,7 @@ KW_FIELD_RHOZ = 7
 # every symbol include/kw.h declares
 EXPORTS = ("kw_workspace_size", "kw_create", "kw_step", "kw_gather", "kw_gather_bytes",
            "kw_set_field", "kw_gather_field", "kw_profile", "kw_stats", "kw_set_graph",
-           "kw_set_plan", "kw_destroy", "kw_last_error")
+           "kw_set_plan", "kw_state_bytes", "kw_save", "kw_load", "kw_destroy", "kw_last_error")
 
 
 class KwGrid(C.Structure):
@@ -125,6 +125,12 @@ def load(path: str = LIB_PATH):
     lib.kw_set_graph.argtypes = [C.c_void_p, C.c_int32]
     lib.kw_set_plan.restype = C.c_int
     lib.kw_set_plan.argtypes = [C.c_void_p, C.c_int, P(C.c_int32), C.c_int32, C.c_int32]
+    lib.kw_state_bytes.restype = C.c_int64
+    lib.kw_state_bytes.argtypes = [C.c_void_p]
+    lib.kw_save.restype = C.c_int
+    lib.kw_save.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+    lib.kw_load.restype = C.c_int
+    lib.kw_load.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
     lib.kw_destroy.restype = C.c_int
     lib.kw_destroy.argtypes = [C.c_void_p]
     lib.kw_last_error.restype = C.c_char_p

@@ -1235,6 +1235,107 @@ int kw_set_plan(kw_sim *s, int axis, const int32_t *radices, int32_t n_radices, 
     return KW_OK;
 }
 
+// --- state snapshots ----------------------------------------------------------
+
+namespace {
+
+struct StateHeader {
+    char magic[8];           // "KWSTATE1"
+    int32_t nx, ny, nz;
+    uint32_t flags, record;
+    int32_t capacity, record_start;
+    int64_t n_sensor, steps, payload;
+    double dt, c_ref;
+};
+
+// device regions of the evolving state, in snapshot order
+std::vector<std::pair<void *, size_t>> state_regions(kw_sim *s) {
+    const size_t N = (size_t)s->grid.nx * s->grid.ny * s->grid.nz;
+    const size_t nrec = s->cnt.sen_all ? N : (size_t)s->cnt.n_sen;
+    std::vector<std::pair<void *, size_t>> r;
+    r.emplace_back(s->counters.step, 2 * sizeof(int));
+    for (int i = 0; i < 3; ++i) r.emplace_back(s->buf.u[i], N * sizeof(float));
+    for (int i = 0; i < 3; ++i) r.emplace_back(s->buf.rho[i], N * sizeof(float));
+    r.emplace_back(s->buf.S[0], N * sizeof(float));      // x/y/z-packed spectrum of p
+    if (s->sen.p_max) r.emplace_back(s->sen.p_max, nrec * sizeof(float));
+    if (s->sen.p_sum2) r.emplace_back(s->sen.p_sum2, nrec * sizeof(float));
+    if (s->sen.series)
+        r.emplace_back(s->sen.series, (size_t)s->cnt.capacity * s->cnt.n_sen * sizeof(float));
+    return r;
+}
+
+StateHeader make_header(kw_sim *s) {
+    StateHeader h{};
+    std::memcpy(h.magic, "KWSTATE1", 8);
+    h.nx = s->grid.nx;
+    h.ny = s->grid.ny;
+    h.nz = s->grid.nz;
+    h.flags = s->flags;
+    h.record = s->cnt.record;
+    h.capacity = s->cnt.capacity;
+    h.record_start = s->record_start;
+    h.n_sensor = s->cnt.sen_all ? -1 : s->cnt.n_sen;
+    h.steps = s->steps;
+    h.dt = s->dt;
+    h.c_ref = s->c_ref;
+    for (auto &r : state_regions(s)) h.payload += (int64_t)r.second;
+    return h;
+}
+
+}  // namespace
+
+int64_t kw_state_bytes(kw_sim *s) {
+    if (!s) return -1;
+    return (int64_t)sizeof(StateHeader) + make_header(s).payload;
+}
+
+int kw_save(kw_sim *s, void *dst, size_t dst_bytes, int dst_is_device) {
+    if (!s || !dst) return fail(KW_EINVAL, "NULL argument");
+    const StateHeader h = make_header(s);
+    const size_t need = sizeof h + (size_t)h.payload;
+    if (dst_bytes < need) return fail(KW_EINVAL, "dst has %zu bytes, %zu needed", dst_bytes, need);
+    const hipMemcpyKind kind = dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    char *d = reinterpret_cast<char *>(dst);
+    KW_HIP(hipStreamSynchronize(s->stream));
+    if (dst_is_device) KW_HIP(hipMemcpy(d, &h, sizeof h, hipMemcpyHostToDevice));
+    else std::memcpy(d, &h, sizeof h);
+    size_t off = sizeof h;
+    for (auto &r : state_regions(s)) {
+        KW_HIP(hipMemcpyAsync(d + off, r.first, r.second, kind, s->stream));
+        off += r.second;
+    }
+    KW_HIP(hipStreamSynchronize(s->stream));
+    return KW_OK;
+}
+
+int kw_load(kw_sim *s, const void *src, size_t src_bytes, int src_is_device) {
+    if (!s || !src) return fail(KW_EINVAL, "NULL argument");
+    StateHeader h{};
+    if (src_bytes < sizeof h) return fail(KW_EINVAL, "snapshot too small");
+    const char *p = reinterpret_cast<const char *>(src);
+    KW_HIP(hipStreamSynchronize(s->stream));
+    if (src_is_device) KW_HIP(hipMemcpy(&h, p, sizeof h, hipMemcpyDeviceToHost));
+    else std::memcpy(&h, p, sizeof h);
+    const StateHeader me = make_header(s);
+    if (std::memcmp(h.magic, me.magic, 8) != 0) return fail(KW_EINVAL, "not a kw state snapshot");
+    if (h.nx != me.nx || h.ny != me.ny || h.nz != me.nz || h.flags != me.flags ||
+        h.record != me.record || h.capacity != me.capacity || h.record_start != me.record_start ||
+        h.n_sensor != me.n_sensor || h.payload != me.payload || h.dt != me.dt || h.c_ref != me.c_ref)
+        return fail(KW_EINVAL, "snapshot was taken from a simulation with another set-up");
+    if (src_bytes < sizeof h + (size_t)h.payload)
+        return fail(KW_EINVAL, "snapshot truncated: %zu of %zu bytes", src_bytes,
+                    sizeof h + (size_t)h.payload);
+    const hipMemcpyKind kind = src_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    size_t off = sizeof h;
+    for (auto &r : state_regions(s)) {
+        KW_HIP(hipMemcpyAsync(r.first, p + off, r.second, kind, s->stream));
+        off += r.second;
+    }
+    KW_HIP(hipStreamSynchronize(s->stream));
+    s->steps = h.steps;
+    return KW_OK;
+}
+
 int kw_destroy(kw_sim *s) {
     if (!s) return KW_OK;
     (void)hipStreamSynchronize(s->stream);

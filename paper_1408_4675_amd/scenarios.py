@@ -21,7 +21,7 @@ from __future__ import annotations
 
 import dataclasses
 from dataclasses import dataclass, field
-from typing import List, Optional, Sequence, Tuple, Union
+from typing import Dict, List, Optional, Sequence, Tuple, Union
 
 import numpy as np
 
@@ -329,20 +329,34 @@ class Request:
 
 
 def serving_trace(seed: int = 0, n_requests: int = 200, rate: float = 20.0,
-                  sizes: Sequence[int] = SERVING_SIZES) -> List[Request]:
+                  sizes: Sequence[int] = SERVING_SIZES, medium_pool: Optional[int] = None,
+                  steps_range: Tuple[int, int] = (300, 1500)) -> List[Request]:
     """Poisson arrivals; per request a cubic grid from `sizes`, a seeded
-    layered medium, a bowl scaled with the grid, 0.5-6 MPa and 300-1500
-    steps; p_max and p_rms recorded at every point."""
+    layered medium, a bowl scaled with the grid, 0.5-6 MPa and a step count
+    drawn from `steps_range` (inclusive); p_max and p_rms recorded at every
+    point.  With `medium_pool` = K, each size has K seeded media that requests
+    of that size share (the draw of the request picks one), which bounds the
+    host time and memory of building a long trace."""
     rng = np.random.default_rng(seed)
     t = 0.0
     out = []
+    pool: Dict[Tuple[int, int], Scenario] = {}
     for rid in range(n_requests):
         t += rng.exponential(1.0 / rate)
         n = int(rng.choice(np.asarray(sizes)))
         amp = float(rng.uniform(0.5e6, 6.0e6))
-        steps = int(rng.integers(300, 1501))
-        sc = tissue_bowl(seed=int(rng.integers(0, 2**31 - 1)), n=n, steps=steps, amp=amp,
-                         pml=10 if n < 128 else 20)
+        steps = int(rng.integers(steps_range[0], steps_range[1] + 1))
+        mseed = int(rng.integers(0, 2**31 - 1))
+        pml = 10 if n < 128 else 20
+        if medium_pool:
+            key = (n, mseed % medium_pool)
+            if key not in pool:
+                pool[key] = tissue_bowl(seed=key[1], n=n, steps=1, pml=pml)
+            base = pool[key]
+            src = dataclasses.replace(base.source, amp=np.array([amp], np.float32))
+            sc = base.replace(source=src, steps=steps)
+        else:
+            sc = tissue_bowl(seed=mseed, n=n, steps=steps, amp=amp, pml=pml)
         out.append(Request(rid, t, sc.replace(name="req%03d_%d" % (rid, n))))
     return out
 

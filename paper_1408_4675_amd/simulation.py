@@ -161,6 +161,36 @@ class Simulation:
         A.check(self.lib.kw_gather_field(self.handle, field, C.c_void_p(out.ctypes.data), 0))
         return out
 
+    def state_bytes(self) -> int:
+        return int(self.lib.kw_state_bytes(self.handle))
+
+    def save(self, device: bool = True):
+        """Snapshot of the evolving state (uint8 tensor on the GPU, or a numpy
+        array in host memory when device is False)."""
+        nb = self.state_bytes()
+        if device:
+            out = torch.empty(nb, dtype=torch.uint8, device=self.device)
+            ptr, isdev = out.data_ptr(), 1
+            torch.cuda.current_stream(self.device).synchronize()
+        else:
+            out = np.empty(nb, np.uint8)
+            ptr, isdev = out.ctypes.data, 0
+        A.check(self.lib.kw_save(self.handle, C.c_void_p(ptr), C.c_size_t(nb), isdev))
+        return out
+
+    def load(self, snapshot):
+        """Restore a snapshot taken with save() from a simulation of the same set-up."""
+        if isinstance(snapshot, torch.Tensor):
+            v = snapshot.contiguous()
+            if v.is_cuda:
+                torch.cuda.current_stream(v.device).synchronize()
+                A.check(self.lib.kw_load(self.handle, C.c_void_p(v.data_ptr()),
+                                         C.c_size_t(v.numel() * v.element_size()), 1))
+                return
+            snapshot = v.numpy()
+        a = np.ascontiguousarray(snapshot, np.uint8)
+        A.check(self.lib.kw_load(self.handle, C.c_void_p(a.ctypes.data), C.c_size_t(a.size), 0))
+
     def profile(self, on: bool):
         A.check(self.lib.kw_profile(self.handle, 1 if on else 0))
 

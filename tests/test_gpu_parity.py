@@ -320,3 +320,51 @@ def test_water_bowl_1024_full_size_properties(kw):
     err = float(np.abs(band - band.transpose(0, 2, 1)).max() / np.abs(band).max())
     print("  x<->y symmetry error %.2e" % err)
     assert err < 1e-4
+
+
+# ---------------------------------------------------------------------------
+# checkpoint / restart (state snapshots)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mask,on_device", [(True, True), (False, False)])
+def test_snapshot_resume_is_bitwise(kw, mask, on_device):
+    """Run 30 steps straight, or 13 steps, snapshot, restore into a fresh
+    simulation and run 17 more: every recorded output is bit-for-bit equal."""
+    A, Simulation = kw
+    scen = sc.small_case(40, 18, 24, seed=21, steps=30, sensor_mask=mask)
+    _banner("snapshot resume mask=%s device=%s" % (mask, on_device))
+    ref = Simulation(scen)
+    ref.step(30)
+    first = Simulation(scen)
+    first.step(13)
+    snap = first.save(device=on_device)
+    first.close()
+    second = Simulation(scen)
+    second.load(snap)
+    second.step(17)
+    assert second.stats()["steps"] == 30
+    whats = [A.KW_REC_P_FINAL, A.KW_REC_U_FINAL]
+    whats += [A.KW_REC_P_SERIES] if mask else [A.KW_REC_P_MAX, A.KW_REC_P_RMS]
+    for what in whats:
+        a = ref.gather(what, device=False)
+        b = second.gather(what, device=False)
+        assert np.array_equal(a, b), what
+
+
+def test_snapshot_rejects_other_setup(kw):
+    A, Simulation = kw
+    s1 = Simulation(sc.small_case(40, 18, 24, seed=21, steps=4))
+    s1.step(2)
+    snap = s1.save(device=False)
+    s2 = Simulation(sc.small_case(40, 18, 20, seed=21, steps=4))
+    with pytest.raises(A.KwError) as e:
+        s2.load(snap)
+    assert e.value.code == A.KW_EINVAL
+    s3 = Simulation(sc.small_case(40, 18, 24, seed=21, steps=4))
+    with pytest.raises(A.KwError) as e:
+        s3.load(snap[: len(snap) // 2])
+    assert e.value.code == A.KW_EINVAL
+    bad = snap.copy()
+    bad[:8] = 0
+    with pytest.raises(A.KwError):
+        s3.load(bad)

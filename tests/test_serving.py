@@ -1,0 +1,59 @@
+"""Serving loop: results identical alone and mixed, admission within the
+HBM budget (GPU), and the trace and summary logic (CPU)."""
+import numpy as np
+import pytest
+
+from paper_1408_4675_amd import scenarios as sc
+from paper_1408_4675_amd.serving import Result, summarize
+
+
+def test_trace_is_poisson_with_the_requested_sizes():
+    reqs = sc.serving_trace(seed=3, n_requests=400, rate=20.0, sizes=(32, 48), medium_pool=2,
+                            steps_range=(5, 9))
+    t = np.array([r.arrival for r in reqs])
+    gaps = np.diff(np.concatenate([[0.0], t]))
+    assert np.all(gaps > 0)
+    assert abs(gaps.mean() - 1 / 20.0) < 0.15 / 20.0          # mean inter-arrival 50 ms
+    assert {r.scenario.grid.nx for r in reqs} == {32, 48}
+    assert all(5 <= r.scenario.steps <= 9 for r in reqs)
+    # pooled media are shared, amplitudes are per request
+    same = [r for r in reqs if r.scenario.grid.nx == 32]
+    ids = {id(r.scenario.medium.c0) for r in same}
+    assert len(ids) <= 2
+    amps = {float(r.scenario.source.amp[0]) for r in same}
+    assert len(amps) == len(same)
+
+
+def test_summary_percentiles():
+    rs = [Result(i, 100, 10, arrival=float(i), start=float(i), finish=float(i) + 1.0 + i * 0.01)
+          for i in range(101)]
+    s = summarize(rs)
+    assert s["requests"] == 101
+    assert abs(s["p50_latency_s"] - 1.5) < 1e-9
+    assert abs(s["p99_latency_s"] - 1.99) < 1e-9
+    assert abs(s["makespan_s"] - (100 + 2.0)) < 1e-9
+    assert abs(s["point_updates_per_s"] - 101 * 1000 / 102.0) < 1e-9
+
+
+@pytest.mark.gpu
+def test_mixed_results_equal_alone_and_budget_holds():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1408_4675_amd.serving import Server, run_fifo
+    from paper_1408_4675_amd.simulation import workspace_size
+    reqs = sc.serving_trace(seed=5, n_requests=8, rate=400.0, sizes=(32, 48, 64),
+                            medium_pool=2, steps_range=(20, 60))
+    print("\n[case] serving: 8 requests of 32^3-64^3, mixed vs alone", flush=True)
+    alone = {r.rid: r for r in run_fifo(reqs, keep_outputs=True)}
+    foot = max(workspace_size(r.scenario) for r in reqs)
+    srv = Server(budget_bytes=2 * foot + 1, max_active=4, chunk_steps=16, keep_outputs=True)
+    mixed = srv.run(reqs)
+    assert srv.peak_used <= 2 * foot + 1
+    assert srv.peak_active >= 2
+    assert len(mixed) == len(reqs)
+    for r in mixed:
+        a = alone[r.rid]
+        assert set(r.outputs) == set(a.outputs) and r.outputs
+        for k in r.outputs:
+            assert np.array_equal(r.outputs[k], a.outputs[k]), (r.rid, k)
