@@ -178,6 +178,10 @@ class Oracle:
                             signal=None if src.signal is None
                             else np.asarray(src.signal, np.float64))
 
+        # optional tape for the discrete adjoint (oracle/adjoint.py): when a
+        # list, every step appends the values its reverse pass needs
+        self.tape = None
+
         # state: p^n, u^(n-1/2), rho_xi^n
         self.p = np.zeros(shape)
         self.u = [np.zeros(shape) for _ in range(3)]
@@ -268,6 +272,9 @@ class Oracle:
                 flat = self.rho[a].reshape(-1)
                 np.add.at(flat, s["idx"], add)
         rho = self.rho[0] + self.rho[1] + self.rho[2]
+        if self.tape is not None:
+            self.tape.append(dict(n=self.n, div=[d.copy() for d in div],
+                                  rho_parts=[r.copy() for r in self.rho], rho=rho.copy()))
         # (8) absorption and dispersion through the fractional Laplacians
         if self.absorbing:
             dudt_term = self.ift(self.k_tau * self.ft(self.rho0 * (div[0] + div[1] + div[2])))
@@ -281,6 +288,8 @@ class Oracle:
         else:
             self.p = self.c0 ** 2 * (rho - L_d)
         self.n += 1
+        if self.tape is not None:
+            self.tape[-1]["p"] = self.p.copy()
         self._record()
 
     def _record(self):

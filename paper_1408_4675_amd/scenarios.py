@@ -318,6 +318,27 @@ def adjoint_bowl(seed: int = 0, n: int = 128, steps: int = 600,
     return Scenario("adjoint_bowl_%d" % n, g, med, src, sen, steps), focus
 
 
+def focal_weights(grid: Grid, focus: Sequence[int], radius: float) -> np.ndarray:
+    """Weights w of the focusing objective sum_x w(x) I(x): +1/|S_in| at the
+    points within `radius` [m] of the focus (grid indices ix, iy, iz), -1/|S_out|
+    at every other point outside the PML, 0 in the PML.  Flat float64 array."""
+    z, y, x = np.meshgrid(np.arange(grid.nz) * grid.dz, np.arange(grid.ny) * grid.dy,
+                          np.arange(grid.nx) * grid.dx, indexing="ij")
+    fx, fy, fz = focus[0] * grid.dx, focus[1] * grid.dy, focus[2] * grid.dz
+    inside = (x - fx) ** 2 + (y - fy) ** 2 + (z - fz) ** 2 <= radius * radius
+    core = np.zeros(grid.shape, bool)
+    px, py, pz = grid.pml_size
+    core[pz:grid.nz - pz, py:grid.ny - py, px:grid.nx - px] = True
+    inside &= core
+    outside = core & ~inside
+    w = np.zeros(grid.shape)
+    if inside.any():
+        w[inside] = 1.0 / inside.sum()
+    if outside.any():
+        w[outside] = -1.0 / outside.sum()
+    return w.reshape(-1)
+
+
 SERVING_SIZES = (64, 96, 128, 160, 192, 256)
 
 
