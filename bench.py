@@ -178,6 +178,58 @@ def serving_bench(n_requests, rate=20.0, seed=0):
     return out
 
 
+def adjoint_bench(checkpoint_every=50, fd_params=4):
+    """Gradient of J = mean intensity in a 2 mm sphere at the focus minus the
+    mean outside, with respect to the 64 element amplitudes and phases, on the
+    128^3 tissue bowl (600 steps, intensity over the last 200).  Reports the
+    forward and reverse wall times and a central-difference check of a few
+    parameters through the float32 forward model."""
+    from paper_1408_4675_amd import scenarios as sc
+    from paper_1408_4675_amd.adjoint import focus_gradient, with_drive, _Run
+    scen, focus = sc.adjoint_bowl(seed=0)
+    w = sc.focal_weights(scen.grid, focus, 2e-3)
+    rng = np.random.default_rng(1)
+    ne = len(scen.source.amp)
+    amp = rng.uniform(0.5e6, 1.5e6, ne)
+    ph = rng.uniform(-np.pi, np.pi, ne)
+    scen = with_drive(scen, amp, ph)
+    log("adjoint: warm-up")
+    focus_gradient(scen.replace(steps=60, sensor=sc.Sensor(record=sc.REC_INTENSITY,
+                                                           record_start=41)), w, checkpoint_every)
+    log("adjoint: gradient")
+    out = focus_gradient(scen, w, checkpoint_every)
+    steps = scen.steps
+    res = dict(metric="focusing-objective gradient (128^3 tissue, 64 elements, 600 steps)",
+               J=out["J"], steps=steps, checkpoint_every=checkpoint_every,
+               forward_s=round(out["forward_s"], 4), backward_s=round(out["backward_s"], 4),
+               forward_ms_per_step=round(out["forward_s"] / steps * 1e3, 4),
+               backward_ms_per_step=round(out["backward_s"] / steps * 1e3, 4),
+               grad_amp_norm=float(np.linalg.norm(out["grad_amp"])),
+               grad_phase_norm=float(np.linalg.norm(out["grad_phase"])))
+    # central differences through the float32 forward model
+    checks = []
+    pick = np.argsort(-np.abs(out["grad_amp"]))[: fd_params // 2]
+    for e in pick:
+        for kind in ("amp", "phase"):
+            a2, p2 = amp.copy(), ph.copy()
+            h = 1e-2 * amp[e] if kind == "amp" else 1e-2
+            vals = []
+            for sgn in (1, -1):
+                if kind == "amp":
+                    a2[e] = amp[e] + sgn * h
+                else:
+                    p2[e] = ph[e] + sgn * h
+                r = _Run(with_drive(scen, a2, p2), w, checkpoint_every)
+                vals.append(r.J)
+                r.close()
+            fd = (vals[0] - vals[1]) / (2 * h)
+            g = out["grad_amp"][e] if kind == "amp" else out["grad_phase"][e]
+            checks.append(dict(element=int(e), param=kind, adjoint=float(g), fd=float(fd),
+                               rel_diff=float(abs(g - fd) / max(abs(fd), 1e-300))))
+    res["fd_checks"] = checks
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -189,6 +241,9 @@ def main():
     ap.add_argument("--serving", type=int, default=0, metavar="N",
                     help="instead of the step benchmark, serve the first N requests of the "
                          "Poisson trace (20/s, 64^3-256^3 tissue) batched and one at a time")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="instead of the step benchmark, time the gradient of the focusing "
+                         "objective (128^3 tissue, 64-element bowl, 600 steps)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -201,6 +256,9 @@ def main():
     _abi.load()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
+    if args.adjoint:
+        print(json.dumps(adjoint_bench()), flush=True)
+        return
     if args.serving:
         print(json.dumps(serving_bench(args.serving)), flush=True)
         return

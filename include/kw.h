@@ -204,6 +204,43 @@ int64_t kw_state_bytes(kw_sim *sim);
 int kw_save(kw_sim *sim, void *dst, size_t dst_bytes, int dst_is_device);
 int kw_load(kw_sim *sim, const void *src, size_t src_bytes, int src_is_device);
 
+/* Reverse mode: the discrete adjoint of kw_step for the objective
+ *   J = sum_x w(x) I(x),  I(x) = (1/N_w) sum_m p^m(x)^2 / (rho0 c0)(x),
+ * the time-mean intensity over the recorded steps m = record_start..n_steps
+ * (sensor.record_start of the simulation; the intensity output of Section 5),
+ * differentiated with respect to the drive values s_e(n) of the source
+ * elements and, for a sinusoidal drive, their amplitudes and phases.  Each
+ * reverse step applies the transpose of one forward step, Eqs. (4a)-(4d), (6),
+ * (8), in float32 on the GPU, using the forward state after that step.
+ *
+ *   kw_adjoint_workspace_size  device bytes for n_steps forward steps (0 on error)
+ *   kw_adjoint_create  weights: host array of nx*ny*nz floats w(x); the adjoint
+ *                      borrows the caller-owned device workspace, uses the
+ *                      simulation's stream and spectral scratch, and keeps a
+ *                      pointer to `sim` (which must outlive it).  The source
+ *                      must be set (KW_EINVAL otherwise).
+ *   kw_adjoint_step    reverse step n: `sim` must hold the state after forward
+ *                      step n (for example restored with kw_load), else
+ *                      KW_ESTATE; call it for n = n_steps-1 down to 0.  Between
+ *                      reverse steps the simulation may be stepped or loaded
+ *                      freely (the adjoint state lives in its own workspace).
+ *   kw_adjoint_objective  J of the forward run, once `sim` holds the state after
+ *                      its last step n_steps - 1 (needs p_rms or intensity
+ *                      recorded at every point); float64 sum on the device
+ *   kw_adjoint_source_gradient  dJ/ds_e(n) as double [n_steps][n_elements] (host)
+ *   kw_adjoint_gradient  dJ/da_e and dJ/dphi_e (host, n_elements each); needs a
+ *                      sinusoidal drive (KW_EINVAL for a sampled signal)
+ *   kw_adjoint_destroy frees host state only; NULL-safe. */
+typedef struct kw_adj kw_adj;
+size_t kw_adjoint_workspace_size(kw_sim *sim, int32_t n_steps);
+int kw_adjoint_create(kw_sim *sim, const float *weights, int32_t n_steps, void *dev_workspace,
+                      size_t ws_bytes, kw_adj **out);
+int kw_adjoint_objective(kw_adj *adj, double *J);
+int kw_adjoint_step(kw_adj *adj, int32_t n);
+int kw_adjoint_source_gradient(kw_adj *adj, double *dJds, size_t dst_bytes);
+int kw_adjoint_gradient(kw_adj *adj, double *grad_amp, double *grad_phase);
+int kw_adjoint_destroy(kw_adj *adj);
+
 /* Free library-owned host state (never the workspace).  NULL-safe. */
 int kw_destroy(kw_sim *sim);
 

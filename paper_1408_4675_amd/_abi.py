@@ -39,7 +39,9 @@ KW_FIELD_RHOZ = 7
 # every symbol include/kw.h declares
 EXPORTS = ("kw_workspace_size", "kw_create", "kw_step", "kw_gather", "kw_gather_bytes",
            "kw_set_field", "kw_gather_field", "kw_profile", "kw_stats", "kw_set_graph",
-           "kw_set_plan", "kw_state_bytes", "kw_save", "kw_load", "kw_destroy", "kw_last_error")
+           "kw_set_plan", "kw_state_bytes", "kw_save", "kw_load", "kw_adjoint_workspace_size",
+           "kw_adjoint_create", "kw_adjoint_objective", "kw_adjoint_step", "kw_adjoint_source_gradient",
+           "kw_adjoint_gradient", "kw_adjoint_destroy", "kw_destroy", "kw_last_error")
 
 
 class KwGrid(C.Structure):
@@ -131,6 +133,21 @@ def load(path: str = LIB_PATH):
     lib.kw_save.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
     lib.kw_load.restype = C.c_int
     lib.kw_load.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+    lib.kw_adjoint_workspace_size.restype = C.c_size_t
+    lib.kw_adjoint_workspace_size.argtypes = [C.c_void_p, C.c_int32]
+    lib.kw_adjoint_create.restype = C.c_int
+    lib.kw_adjoint_create.argtypes = [C.c_void_p, P(C.c_float), C.c_int32, C.c_void_p,
+                                      C.c_size_t, P(C.c_void_p)]
+    lib.kw_adjoint_objective.restype = C.c_int
+    lib.kw_adjoint_objective.argtypes = [C.c_void_p, P(C.c_double)]
+    lib.kw_adjoint_step.restype = C.c_int
+    lib.kw_adjoint_step.argtypes = [C.c_void_p, C.c_int32]
+    lib.kw_adjoint_source_gradient.restype = C.c_int
+    lib.kw_adjoint_source_gradient.argtypes = [C.c_void_p, P(C.c_double), C.c_size_t]
+    lib.kw_adjoint_gradient.restype = C.c_int
+    lib.kw_adjoint_gradient.argtypes = [C.c_void_p, P(C.c_double), P(C.c_double)]
+    lib.kw_adjoint_destroy.restype = C.c_int
+    lib.kw_adjoint_destroy.argtypes = [C.c_void_p]
     lib.kw_destroy.restype = C.c_int
     lib.kw_destroy.argtypes = [C.c_void_p]
     lib.kw_last_error.restype = C.c_char_p

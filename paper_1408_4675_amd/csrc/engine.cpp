@@ -441,6 +441,10 @@ struct kw_sim {
     };
     std::vector<Rec> recs;
     std::vector<hipEvent_t> pool;
+    // host copy of the source set-up (for the reverse-mode step)
+    std::vector<int> src_flat, src_elem;
+    std::vector<float> src_coef;
+    std::vector<double> src_amp, src_phase;
     double class_ms[KC_COUNT] = {0};
     long class_n[KC_COUNT] = {0};
     double class_bytes[KC_COUNT] = {0};
@@ -533,12 +537,12 @@ hipError_t enqueue_step(kw_sim *s) {
     float2 *s123[3] = {S[1], S[2], S[3]};
     float2 *s456[3] = {S[4], S[5], S[6]};
     KW_L(KC_YFWD, 2, launch_ypass(st, g, c, t, s0, 1, false, &s->counters, &s->src));
-    KW_L(KC_ZGRAD, 4, launch_zfused(st, g, c, t, 0, s0, s123));
+    KW_L(KC_ZGRAD, 4, launch_zfused(st, g, c, t, ZM_GRAD, s0, s123));
     KW_L(KC_YINV, 6, launch_ypass(st, g, c, t, s123, 3, true, nullptr, nullptr));
     KW_L(KC_XVEL, 12 + (ms.het[MED_DTRX] ? 3 : 0),
          launch_xvel(st, g, c, t, s->med, s123, s->buf.u));
     KW_L(KC_YFWD, 6, launch_ypass(st, g, c, t, s123, 3, false, nullptr, nullptr));
-    KW_L(KC_ZDIV, 6, launch_zfused(st, g, c, t, 1, s123, s456));
+    KW_L(KC_ZDIV, 6, launch_zfused(st, g, c, t, ZM_DIV, s123, s456));
     KW_L(KC_YINV, 6, launch_ypass(st, g, c, t, s456, 3, true, nullptr, nullptr));
     if (absorbing) {
         float2 *out2[2] = {S[1], S[2]};
@@ -548,7 +552,7 @@ hipError_t enqueue_step(kw_sim *s) {
         float2 *s12[2] = {S[1], S[2]};
         float2 *s45[2] = {S[4], S[5]};
         KW_L(KC_YFWD, 4, launch_ypass(st, g, c, t, s12, 2, false, nullptr, nullptr));
-        KW_L(KC_ZABS, 4, launch_zfused(st, g, c, t, 2, s12, s45));
+        KW_L(KC_ZABS, 4, launch_zfused(st, g, c, t, ZM_ABS, s12, s45));
         KW_L(KC_YINV, 4, launch_ypass(st, g, c, t, s45, 2, true, nullptr, nullptr));
         const double med_units = (ms.het[MED_C0SQ] ? 1 : 0) + (ms.het[MED_NL] ? 1 : 0) +
                                  (ms.het[MED_TA] ? 2 : 0);
@@ -895,6 +899,12 @@ int kw_create(const kw_grid *grid, const kw_medium *medium, const kw_source *sou
         sd.amp_sin = s->at<double>(L.src_as);
         sd.n_elements = cnt.n_elem;
         sd.omega_dt = 2.0 * kPi * source->freq * dt;
+        s->src_flat.resize(ns);
+        for (long i = 0; i < ns; ++i) s->src_flat[i] = (int)source->index[i];
+        s->src_elem = el;
+        s->src_coef = cf;
+        s->src_amp.assign(source->amp, source->amp + cnt.n_elem);
+        s->src_phase.assign(source->phase, source->phase + cnt.n_elem);
         if (cnt.n_samples > 0) {
             put(L.src_sig, source->signal, (size_t)cnt.n_elem * cnt.n_samples * sizeof(float));
             sd.signal = s->at<float>(L.src_sig);
@@ -1333,6 +1343,216 @@ int kw_load(kw_sim *s, const void *src, size_t src_bytes, int src_is_device) {
     }
     KW_HIP(hipStreamSynchronize(s->stream));
     s->steps = h.steps;
+    return KW_OK;
+}
+
+// --- reverse mode ---------------------------------------------------------------
+
+struct kw_adj {
+    kw_sim *sim = nullptr;
+    AdjDev a{};
+    int n_steps = 0;
+};
+
+namespace {
+
+struct AdjLayout {
+    size_t fld[16];          // pb, ub x3, rb x3, d x3, T x3, pf, w, rbt
+    size_t dJds, obj, flat, elem, coef, corr, total;
+};
+
+AdjLayout adj_layout(const kw_sim *s, int n_steps) {
+    AdjLayout L{};
+    Carver cv;
+    const size_t N = (size_t)s->grid.nx * s->grid.ny * s->grid.nz;
+    for (int i = 0; i < 16; ++i) L.fld[i] = cv.take(N * sizeof(float));
+    const size_t ns = s->src_flat.size();
+    L.dJds = cv.take((size_t)std::max(1, n_steps) * std::max(1, s->cnt.n_elem) * sizeof(double));
+    L.obj = cv.take(sizeof(double));
+    L.flat = cv.take(std::max<size_t>(ns, 1) * sizeof(int));
+    L.elem = cv.take(std::max<size_t>(ns, 1) * sizeof(int));
+    L.coef = cv.take(std::max<size_t>(ns, 1) * sizeof(float));
+    L.corr = cv.take(3 * std::max<size_t>(ns, 1) * sizeof(float));
+    L.total = cv.off;
+    return L;
+}
+
+// out[j] = IFT(m_j FT in[j]) for j < k, through the forward passes and the
+// spectral scratch S1..S6 of the simulation (free between steps)
+hipError_t spectral(kw_sim *s, int mode, float *const *in, float *const *out, int k) {
+    hipStream_t st = s->stream;
+    const GridDev &g = s->g;
+    const LaunchCfg &c = s->cfg;
+    const Tables &t = s->tab;
+    float2 *sin[3] = {s->buf.S[1], s->buf.S[2], s->buf.S[3]};
+    float2 *sout[3] = {s->buf.S[4], s->buf.S[5], s->buf.S[6]};
+    hipError_t e;
+    for (int j = 0; j < k; ++j)
+        if ((e = launch_xfwd(st, g, c, t, in[j], sin[j])) != hipSuccess) return e;
+    if ((e = launch_ypass(st, g, c, t, sin, k, false, nullptr, nullptr)) != hipSuccess) return e;
+    if ((e = launch_zfused(st, g, c, t, mode, sin, sout)) != hipSuccess) return e;
+    if ((e = launch_ypass(st, g, c, t, sout, k, true, nullptr, nullptr)) != hipSuccess) return e;
+    for (int j = 0; j < k; ++j)
+        if ((e = launch_xinv(st, g, c, t, sout[j], out[j], 1.0f)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+}  // namespace
+
+size_t kw_adjoint_workspace_size(kw_sim *s, int32_t n_steps) {
+    if (!s || n_steps < 1) {
+        fail(KW_EINVAL, "sim is NULL or n_steps < 1");
+        return 0;
+    }
+    return adj_layout(s, n_steps).total;
+}
+
+int kw_adjoint_create(kw_sim *s, const float *weights, int32_t n_steps, void *dev_workspace,
+                      size_t ws_bytes, kw_adj **out) {
+    if (!s || !weights || !dev_workspace || !out) return fail(KW_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (n_steps < 1) return fail(KW_EINVAL, "n_steps must be >= 1");
+    if (s->src_flat.empty()) return fail(KW_EINVAL, "the simulation has no source");
+    const int n_window = n_steps - s->record_start + 1;
+    if (n_window < 1)
+        return fail(KW_EINVAL, "no recorded step: record_start %d > n_steps %d", s->record_start,
+                    n_steps);
+    const AdjLayout L = adj_layout(s, n_steps);
+    if (ws_bytes < L.total)
+        return fail(KW_ENOMEM, "adjoint workspace has %zu bytes, %zu needed", ws_bytes, L.total);
+    char *ws = reinterpret_cast<char *>(dev_workspace);
+    kw_adj *adj = new kw_adj;
+    adj->sim = s;
+    adj->n_steps = n_steps;
+    AdjDev &a = adj->a;
+    auto F = [&](int i) { return reinterpret_cast<float *>(ws + L.fld[i]); };
+    a.pb = F(0);
+    for (int i = 0; i < 3; ++i) {
+        a.ub[i] = F(1 + i);
+        a.rb[i] = F(4 + i);
+        a.d[i] = F(7 + i);
+        a.T[i] = F(10 + i);
+    }
+    a.pf = F(13);
+    a.w = F(14);
+    a.rbt = F(15);
+    a.dJds = reinterpret_cast<double *>(ws + L.dJds);
+    a.obj = reinterpret_cast<double *>(ws + L.obj);
+    a.n_steps = n_steps;
+    a.n_elem = s->cnt.n_elem;
+    a.n_src = (int)s->src_flat.size();
+    a.src_flat = reinterpret_cast<int *>(ws + L.flat);
+    a.src_elem = reinterpret_cast<int *>(ws + L.elem);
+    a.src_coef = reinterpret_cast<float *>(ws + L.coef);
+    a.corr = reinterpret_cast<float *>(ws + L.corr);
+    const size_t N = (size_t)s->grid.nx * s->grid.ny * s->grid.nz;
+    hipStream_t st = s->stream;
+    auto bail = [&](hipError_t e) {
+        delete adj;
+        return fail(KW_EDEVICE, "adjoint set-up: %s", hipGetErrorString(e));
+    };
+    hipError_t e;
+    if ((e = hipMemcpyAsync(a.w, weights, N * sizeof(float), hipMemcpyHostToDevice, st)) != hipSuccess)
+        return bail(e);
+    if ((e = launch_adj_weights(st, s->g, s->med, a.w, (float)(2.0 / n_window))) != hipSuccess)
+        return bail(e);
+    const size_t ns = s->src_flat.size();
+    if ((e = hipMemcpyAsync(ws + L.flat, s->src_flat.data(), ns * sizeof(int), hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(ws + L.elem, s->src_elem.data(), ns * sizeof(int), hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(ws + L.coef, s->src_coef.data(), ns * sizeof(float), hipMemcpyHostToDevice, st)) != hipSuccess)
+        return bail(e);
+    for (int i = 0; i < 7; ++i)   // pb, ub, rb start at zero
+        if ((e = launch_fill(st, F(i), N, 0.0f)) != hipSuccess) return bail(e);
+    if ((e = hipMemsetAsync(a.dJds, 0, (size_t)n_steps * a.n_elem * sizeof(double), st)) != hipSuccess)
+        return bail(e);
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return bail(e);
+    *out = adj;
+    return KW_OK;
+}
+
+int kw_adjoint_step(kw_adj *adj, int32_t n) {
+    if (!adj) return fail(KW_EINVAL, "adj is NULL");
+    kw_sim *s = adj->sim;
+    if (n < 0 || n >= adj->n_steps) return fail(KW_EINVAL, "step %d outside [0, %d)", n, adj->n_steps);
+    if (s->steps != (long)n + 1)
+        return fail(KW_ESTATE, "the simulation holds the state after step %ld, not %d", s->steps - 1, n);
+    AdjDev &a = adj->a;
+    hipStream_t st = s->stream;
+    const GridDev &g = s->g;
+    const Medium &m = s->med;
+    hipError_t e;
+#define KW_A(call)                                                                  \
+    do {                                                                            \
+        if ((e = (call)) != hipSuccess)                                             \
+            return fail(KW_EDEVICE, "adjoint step: %s", hipGetErrorString(e));      \
+    } while (0)
+    // forward divergence of u^(n+1/2) (the nonlinear denominators need it)
+    KW_A(spectral(s, ZM_DIV, s->buf.u, a.d, 3));
+    const bool loss = n + 1 >= s->record_start;
+    if (loss) KW_A(launch_xinv(st, g, s->cfg, s->tab, s->buf.S[0], a.pf, 1.0f / (float)s->grid.nx));
+    KW_A(launch_adj_eos(st, g, m, a, s->buf.rho, loss));
+    if (m.absorbing) KW_A(spectral(s, ZM_ABS, a.T, a.T, 2));
+    KW_A(launch_adj_src(st, g, m, a, s->src, n));
+    KW_A(launch_adj_den(st, g, s->tab, m, a, s->buf.rho));
+    KW_A(launch_adj_src_fix(st, a, m));
+    KW_A(spectral(s, ZM_DIVT, a.d, a.T, 3));
+    KW_A(launch_adj_vel(st, g, s->tab, m, a));
+    KW_A(spectral(s, ZM_GRADT, a.T, a.T, 3));
+    KW_A(launch_adj_sum(st, g, a));
+#undef KW_A
+    return KW_OK;
+}
+
+int kw_adjoint_objective(kw_adj *adj, double *J) {
+    if (!adj || !J) return fail(KW_EINVAL, "NULL argument");
+    kw_sim *s = adj->sim;
+    if (!s->sen.all_points || !s->sen.p_sum2)
+        return fail(KW_EINVAL, "the objective needs p_rms or intensity recorded at every point");
+    if (s->steps != adj->n_steps)
+        return fail(KW_ESTATE, "the simulation holds step %ld, the objective needs step %d",
+                    s->steps, adj->n_steps);
+    KW_HIP(hipMemsetAsync(adj->a.obj, 0, sizeof(double), s->stream));
+    KW_HIP(launch_adj_objective(s->stream, s->g, adj->a.w, s->sen.p_sum2, adj->a.obj));
+    KW_HIP(hipMemcpyAsync(J, adj->a.obj, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    KW_HIP(hipStreamSynchronize(s->stream));
+    return KW_OK;
+}
+
+int kw_adjoint_source_gradient(kw_adj *adj, double *dJds, size_t bytes) {
+    if (!adj || !dJds) return fail(KW_EINVAL, "NULL argument");
+    const size_t need = (size_t)adj->n_steps * adj->a.n_elem * sizeof(double);
+    if (bytes < need) return fail(KW_EINVAL, "dst has %zu bytes, %zu needed", bytes, need);
+    KW_HIP(hipMemcpyAsync(dJds, adj->a.dJds, need, hipMemcpyDeviceToHost, adj->sim->stream));
+    KW_HIP(hipStreamSynchronize(adj->sim->stream));
+    return KW_OK;
+}
+
+int kw_adjoint_gradient(kw_adj *adj, double *grad_amp, double *grad_phase) {
+    if (!adj || !grad_amp || !grad_phase) return fail(KW_EINVAL, "NULL argument");
+    kw_sim *s = adj->sim;
+    if (s->src.signal) return fail(KW_EINVAL, "sampled drive signal: use kw_adjoint_source_gradient");
+    const int ne = adj->a.n_elem, T = adj->n_steps;
+    std::vector<double> d((size_t)T * ne);
+    const int rc = kw_adjoint_source_gradient(adj, d.data(), d.size() * sizeof(double));
+    if (rc != KW_OK) return rc;
+    for (int e = 0; e < ne; ++e) {
+        double ga = 0.0, gp = 0.0;
+        for (int n = 0; n < T; ++n) {
+            // s_e(n) = a_e sin(theta_n + phi_e), theta_n = omega (n + 1/2) dt
+            const double th = s->src.omega_dt * ((double)n + 0.5) + s->src_phase[e];
+            ga += d[(size_t)n * ne + e] * std::sin(th);
+            gp += d[(size_t)n * ne + e] * s->src_amp[e] * std::cos(th);
+        }
+        grad_amp[e] = ga;
+        grad_phase[e] = gp;
+    }
+    return KW_OK;
+}
+
+int kw_adjoint_destroy(kw_adj *adj) {
+    if (!adj) return KW_OK;
+    (void)hipStreamSynchronize(adj->sim->stream);
+    delete adj;
     return KW_OK;
 }
 

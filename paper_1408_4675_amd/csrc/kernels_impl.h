@@ -110,6 +110,15 @@ __device__ __forceinline__ int col0_ky(int r, int ny) {
     return r - (ny - 1 - h);
 }
 
+// Drive value s_e of element e in step n, at t = (n + 1/2) dt (the mass
+// source of Eq. (4d)): a_e sin(omega t + phi_e) = a_e cos(phi_e) sin(omega t)
+// + a_e sin(phi_e) cos(omega t) in float64, or the sampled signal.
+__device__ __forceinline__ float drive_at(const SourceDev &src, int e, int n) {
+    if (src.signal) return (n < src.n_samples) ? src.signal[(size_t)e * src.n_samples + n] : 0.0f;
+    const double th = src.omega_dt * ((double)n + 0.5);
+    return (float)(src.amp_cos[e] * sin(th) + src.amp_sin[e] * cos(th));
+}
+
 // ---------------------------------------------------------------------------
 // y pass: in-place column FFTs of up to three spectra
 // ---------------------------------------------------------------------------
@@ -141,16 +150,7 @@ __global__ void __launch_bounds__(512) kw_ypass(YArgs a) {
         const int n = *a.cnt.step;
         __syncthreads();
         if (tid == 0) *a.cnt.step = n + 1;
-        for (int e = tid; e < a.src.n_elements; e += blockDim.x) {
-            float s;
-            if (a.src.signal) {
-                s = (n < a.src.n_samples) ? a.src.signal[(size_t)e * a.src.n_samples + n] : 0.0f;
-            } else {
-                const double th = a.src.omega_dt * ((double)n + 0.5);
-                s = (float)(a.src.amp_cos[e] * sin(th) + a.src.amp_sin[e] * cos(th));
-            }
-            a.src.drive[e] = s;
-        }
+        for (int e = tid; e < a.src.n_elements; e += blockDim.x) a.src.drive[e] = drive_at(a.src, e, n);
     }
 
     float2 v[E];
@@ -233,7 +233,7 @@ __global__ void __launch_bounds__(512) kw_ypass(YArgs a) {
 // ---------------------------------------------------------------------------
 // fused z pass: forward z FFT -> k-space operator(s) -> inverse z FFT
 // ---------------------------------------------------------------------------
-enum { ZM_GRAD = 0, ZM_DIV = 1, ZM_ABS = 2 };
+// (z-pass modes ZM_* are defined in kw_internal.h)
 
 struct ZArgs {
     int zero;                // always 0 (see the salt in kw_xvel)
@@ -258,10 +258,11 @@ __device__ __forceinline__ float2 z_operator(const ZArgs &a, int o, int ix, int 
     } else {
         const float s = kappa_of_x2(a.g.half_cdt * a.g.half_cdt * k2) * a.g.inv_n;
         float2 d;
-        if (MODE == ZM_GRAD)
+        if (MODE == ZM_GRAD || MODE == ZM_GRADT)
             d = (o == 0) ? a.t.dpx[ix] : (o == 1) ? a.t.dpy[iy] : a.t.dpz[iz];
         else
             d = (o == 0) ? a.t.dmx[ix] : (o == 1) ? a.t.dmy[iy] : a.t.dmz[iz];
+        if constexpr (MODE == ZM_DIVT || MODE == ZM_GRADT) d = c_conj(d);
         return c_scale(d, s);
     }
 }

@@ -29,7 +29,7 @@ hipError_t launch_ypass(hipStream_t s, const GridDev &g, const LaunchCfg &c, con
 static ZArgs make_zargs(const GridDev &g, const LaunchCfg &c, const Tables &t, int mode,
                         float2 *const *in, float2 *const *out) {
     ZArgs a{};
-    const int nin = (mode == ZM_GRAD) ? 1 : (mode == ZM_DIV) ? 3 : 2;
+    const int nin = (mode == ZM_GRAD) ? 1 : (mode == ZM_ABS) ? 2 : 3;
     const int nout = (mode == ZM_ABS) ? 2 : 3;
     for (int i = 0; i < nin; ++i) a.in[i] = in[i];
     for (int i = 0; i < nout; ++i) a.out[i] = out[i];
@@ -54,7 +54,9 @@ hipError_t launch_zfused(hipStream_t s, const GridDev &g, const LaunchCfg &c, co
     KW_ENGINE_SWITCH(c.eng_z, {
         if (mode == ZM_GRAD) hipLaunchKernelGGL((kw_zfused<Eng, ZM_GRAD>), grid, block, lds, s, a);
         else if (mode == ZM_DIV) hipLaunchKernelGGL((kw_zfused<Eng, ZM_DIV>), grid, block, lds, s, a);
-        else hipLaunchKernelGGL((kw_zfused<Eng, ZM_ABS>), grid, block, lds, s, a);
+        else if (mode == ZM_ABS) hipLaunchKernelGGL((kw_zfused<Eng, ZM_ABS>), grid, block, lds, s, a);
+        else if (mode == ZM_DIVT) hipLaunchKernelGGL((kw_zfused<Eng, ZM_DIVT>), grid, block, lds, s, a);
+        else hipLaunchKernelGGL((kw_zfused<Eng, ZM_GRADT>), grid, block, lds, s, a);
     });
     return hipGetLastError();
 }

@@ -148,7 +148,35 @@ inline size_t den_lds_bytes(int M, int nx, int tb, bool line) {
     return (size_t)3 * tb * rp * 8 + (size_t)tb * M * 8 + (line ? (size_t)tb * nx * 4 : 0);
 }
 
-// launchers (kernels_yz.hip, kernels_x.hip, kernels_util.hip) ---------------------
+// GRAD: one input, output o multiplied by D+_o kappa / N          (Eq. (4a))
+// DIV:  input o, output o multiplied by D-_o kappa / N            (Eq. (4c))
+// ABS:  input o multiplied by k^(y-2) / N (o = 0), k^(y-1) / N     (Eq. (8))
+// DIVT, GRADT: input o, output o multiplied by conj(D-_o kappa) / N and
+// conj(D+_o kappa) / N, the transposes of the real operators of DIV and GRAD
+// (used by the reverse-mode step)
+enum { ZM_GRAD = 0, ZM_DIV = 1, ZM_ABS = 2, ZM_DIVT = 3, ZM_GRADT = 4 };
+
+// reverse-mode (adjoint) step state, all device arrays of N floats unless noted
+struct AdjDev {
+    float *pb;               // adjoint of p^(n+1) (carried between reverse steps)
+    float *ub[3];            // adjoint of u^(n+1/2)
+    float *rb[3];            // adjoint of rho_xi^(n+1)
+    float *d[3];             // forward divergence d_xi, then its adjoint
+    float *T[3];             // temporaries
+    float *pf;               // p^(n+1)
+    float *w;                // 2 w / (rho0 c0 N_w): derivative of the objective
+    float *rbt;              // adjoint of rho (the sum of the components)
+    double *dJds;            // [n_steps][n_elements] derivative by the drive values
+    double *obj;             // objective J (one value)
+    int n_steps, n_elem;
+    int n_src;               // source points
+    const int *src_flat;     // flat index, element and coefficient of each point
+    const int *src_elem;
+    const float *src_coef;
+    float *corr;             // [3][n_src] source correction of the divergence adjoint
+};
+
+// launchers (kernels_yz.hip, kernels_x.hip, kernels_util.hip, kernels_adj.hip) ------
 hipError_t launch_ypass(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
                         float2 *const *fields, int nfields, bool inverse,
                         const Counters *prologue, const SourceDev *src);
@@ -168,6 +196,21 @@ hipError_t launch_xfwd(hipStream_t s, const GridDev &g, const LaunchCfg &c, cons
                        const float *src, float2 *dst);
 hipError_t launch_xinv(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
                        const float2 *src, float *dst, float scale);
+// reverse-mode step pieces (kernels_adj.hip)
+hipError_t launch_adj_weights(hipStream_t s, const GridDev &g, const Medium &m, float *w,
+                              float scale);
+hipError_t launch_adj_eos(hipStream_t s, const GridDev &g, const Medium &m, const AdjDev &a,
+                          float *const *rho, bool loss);
+hipError_t launch_adj_src(hipStream_t s, const GridDev &g, const Medium &m, const AdjDev &a,
+                          const SourceDev &src, int n);
+hipError_t launch_adj_den(hipStream_t s, const GridDev &g, const Tables &t, const Medium &m,
+                          const AdjDev &a, float *const *rho);
+hipError_t launch_adj_src_fix(hipStream_t s, const AdjDev &a, const Medium &m);
+hipError_t launch_adj_vel(hipStream_t s, const GridDev &g, const Tables &t, const Medium &m,
+                          const AdjDev &a);
+hipError_t launch_adj_sum(hipStream_t s, const GridDev &g, const AdjDev &a);
+hipError_t launch_adj_objective(hipStream_t s, const GridDev &g, const float *w,
+                                const float *sum2, double *out);
 hipError_t launch_fill(hipStream_t s, float *p, size_t n, float v);
 hipError_t launch_fill_int(hipStream_t s, int *p, size_t n, int v);
 // dst[i] = f(sum2[i]) for the gather of p_rms / intensity

@@ -1,0 +1,86 @@
+"""Reverse-mode step on the GPU (float32, C ABI) versus the FP64 discrete
+adjoint of the oracle, and the autograd wrapper."""
+import numpy as np
+import pytest
+
+from oracle.adjoint import AdjointOracle
+from paper_1408_4675_amd import scenarios as sc
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def kw():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1408_4675_amd import _abi as A
+    A.load()
+    return A
+
+
+def _case(nonlinear, absorbing, heterogeneous, n=(24, 20, 30), steps=40, seed=4, pml=4,
+          elements=4):
+    scen = sc.small_case(*n, seed=seed, heterogeneous=heterogeneous, nonlinear=nonlinear,
+                         absorbing=absorbing, pml=pml, steps=steps, amp=2.0e6,
+                         n_elements=elements)
+    scen = scen.replace(sensor=sc.Sensor(record=sc.REC_INTENSITY, record_start=steps - 15))
+    w = sc.focal_weights(scen.grid, (n[0] // 2, n[1] // 2, n[2] // 2), 4e-4)
+    return scen, w
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+@pytest.mark.parametrize("nonlinear,absorbing,heterogeneous,K",
+                         [(False, False, False, 7), (True, False, True, 50),
+                          (True, True, True, 9), (True, True, True, 1)])
+def test_adjoint_matches_fp64_oracle(kw, nonlinear, absorbing, heterogeneous, K):
+    from paper_1408_4675_amd.adjoint import focus_gradient
+    scen, w = _case(nonlinear, absorbing, heterogeneous)
+    print("\n[case] adjoint nl=%s abs=%s het=%s checkpoint %d" % (nonlinear, absorbing,
+                                                                 heterogeneous, K), flush=True)
+    ref = AdjointOracle(scen, w, workers=8)
+    Jr = ref.forward()
+    gr = ref.backward()
+    out = focus_gradient(scen, w, checkpoint_every=K)
+    rJ = abs(out["J"] - Jr) / abs(Jr)
+    ra = _rel(out["grad_amp"], gr["grad_amp"])
+    rp = _rel(out["grad_phase"], gr["grad_phase"])
+    rs = _rel(out["source_gradient"], gr["dJds"])
+    print("adjoint J %.2e  dJ/da %.2e  dJ/dphi %.2e  dJ/ds %.2e" % (rJ, ra, rp, rs), flush=True)
+    assert rJ < 1e-3 and ra < 1e-3 and rp < 1e-3 and rs < 1e-3
+
+
+def test_autograd_function(kw):
+    import torch
+    from paper_1408_4675_amd.adjoint import FocusObjective
+    scen, w = _case(True, True, True, steps=30)
+    amp = torch.tensor(scen.source.amp.astype(np.float64), requires_grad=True)
+    ph = torch.tensor(scen.source.phase.astype(np.float64), requires_grad=True)
+    J = FocusObjective.apply(amp, ph, scen, w, 10)
+    (2.0 * J).backward()
+    ref = AdjointOracle(scen, w, workers=8)
+    ref.forward()
+    gr = ref.backward()
+    assert _rel(amp.grad.numpy(), 2.0 * gr["grad_amp"]) < 1e-3
+    assert _rel(ph.grad.numpy(), 2.0 * gr["grad_phase"]) < 1e-3
+
+
+def test_adjoint_rejects_wrong_state(kw):
+    from paper_1408_4675_amd.adjoint import Adjoint
+    from paper_1408_4675_amd.simulation import Simulation
+    A = kw
+    scen, w = _case(False, False, False, steps=20)
+    sim = Simulation(scen)
+    adj = Adjoint(sim, w, 10)
+    sim.step(3)
+    with pytest.raises(A.KwError) as e:
+        adj.step(5)                  # the simulation holds step 2
+    assert e.value.code == A.KW_ESTATE
+    with pytest.raises(A.KwError):
+        adj.step(10)
+    adj.step(2)
+    adj.close()
+    sim.close()
