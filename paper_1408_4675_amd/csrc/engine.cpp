@@ -441,6 +441,7 @@ struct kw_sim {
     };
     std::vector<Rec> recs;
     std::vector<hipEvent_t> pool;
+    size_t max_lds = 64 * 1024;        // LDS bytes a block may use on this device
     // host copy of the source set-up (for the reverse-mode step)
     std::vector<int> src_flat, src_elem;
     std::vector<float> src_coef;
@@ -600,10 +601,16 @@ int build_graph(kw_sim *s) {
     return KW_OK;
 }
 
-int check_tb(const char *what, int tb, int L, size_t lds) {
-    if (tb < 1 || tb * L > 512)
+// A block of tb x L threads with `lds` bytes: up to 512 threads and 64 KB, or,
+// for the column passes of the fixed engines (`wide`), up to 1024 threads and
+// the device's LDS per block.
+int check_tb(const char *what, int tb, int L, size_t lds, bool wide = false,
+             size_t max_lds = 64 * 1024) {
+    const int max_threads = wide ? 1024 : 512;
+    const size_t lds_cap = wide ? max_lds : (size_t)64 * 1024;
+    if (tb < 1 || tb * L > max_threads)
         return fail(KW_EUNSUPPORTED, "%s: %d x %d threads exceed a block", what, tb, L);
-    if (lds > 64 * 1024) return fail(KW_EUNSUPPORTED, "%s: %zu bytes of LDS", what, lds);
+    if (lds > lds_cap) return fail(KW_EUNSUPPORTED, "%s: %zu bytes of LDS", what, lds);
     return KW_OK;
 }
 
@@ -630,21 +637,32 @@ int pick_tiles(kw_sim *s, int tile_y, int tile_z) {
             return fail(KW_EUNSUPPORTED, "density pass does not fit a block (nx = %d)", g.nx);
         c.tb_den = best;
     }
-    auto col_tile = [&](int n, int L, int req) {
+    // columns per block of the y and z passes: 16 (128-byte rows of a tile)
+    // where a block can hold them -- for the fixed engines up to 1024 threads
+    // and the device's LDS per block (measured at 1024^3: 120 -> 111 ms per
+    // step against 8 columns of 512 threads), else 512 threads and 64 KB
+    auto col_tile = [&](int n, int L, int req, bool wide) {
         if (req > 0) return req;
+        const int max_threads = wide ? 1024 : 512;
+        const size_t max_bytes = wide ? s->max_lds : (size_t)64 * 1024;
         int tb = 16;
-        while (tb > 1 && (tb * L > 512 || (size_t)tb * n * sizeof(float2) > 64 * 1024)) tb /= 2;
+        while (tb > 1 && (tb * L > max_threads || (size_t)tb * n * sizeof(float2) > max_bytes))
+            tb /= 2;
         return tb;
     };
-    c.tb_y = col_tile(g.ny, c.py.L, tile_y);
-    c.tb_z = col_tile(g.nz, c.pz.L, tile_z);
+    c.tb_y = col_tile(g.ny, c.py.L, tile_y, c.eng_y == ENG_F8 || c.eng_y == ENG_F16);
+    c.tb_z = col_tile(g.nz, c.pz.L, tile_z, c.eng_z == ENG_F8 || c.eng_z == ENG_F16);
     const size_t xl = (size_t)c.tb_x * (g.M + (g.M >> 4) + 1) * sizeof(float2) +
                       (size_t)c.tb_x * g.nx * sizeof(float);
     int rc;
     if ((rc = check_tb("x pass", c.tb_x, c.px.L, xl)) != KW_OK) return rc;
-    if ((rc = check_tb("y pass", c.tb_y, c.py.L, (size_t)c.tb_y * g.ny * sizeof(float2))) != KW_OK)
+    const bool wide_y = c.eng_y == ENG_F8 || c.eng_y == ENG_F16;
+    const bool wide_z = c.eng_z == ENG_F8 || c.eng_z == ENG_F16;
+    if ((rc = check_tb("y pass", c.tb_y, c.py.L, (size_t)c.tb_y * g.ny * sizeof(float2), wide_y,
+                       s->max_lds)) != KW_OK)
         return rc;
-    if ((rc = check_tb("z pass", c.tb_z, c.pz.L, (size_t)c.tb_z * g.nz * sizeof(float2))) != KW_OK)
+    if ((rc = check_tb("z pass", c.tb_z, c.pz.L, (size_t)c.tb_z * g.nz * sizeof(float2), wide_z,
+                       s->max_lds)) != KW_OK)
         return rc;
     return KW_OK;
 }
@@ -975,6 +993,14 @@ int kw_create(const kw_grid *grid, const kw_medium *medium, const kw_source *sou
     for (int i = 0; i < 7; ++i) s->buf.S[i] = s->at<float2>(L.S[i]);
 
     // launch shapes (they depend on the source and sensor set-up above)
+    {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+            v > 0)
+            s->max_lds = (size_t)v;
+        (void)hipGetLastError();
+    }
     if ((rc = pick_tiles(s, 0, 0)) != KW_OK) {
         delete s;
         return rc;

@@ -135,8 +135,10 @@ struct YArgs {
     SourceDev src;
 };
 
-template <class Eng, bool INV>
-__global__ void __launch_bounds__(512) kw_ypass(YArgs a) {
+// MAXT: 512, or 1024 for the wide column tiles of long axes (fixed engines
+// only, whose register count fits the 128 registers a 1024-thread block allows)
+template <class Eng, bool INV, int MAXT = 512>
+__global__ void __launch_bounds__(MAXT) kw_ypass(YArgs a) {
     constexpr int E = Eng::E;
     extern __shared__ float2 sh[];
     const int tid = threadIdx.x;
@@ -274,8 +276,8 @@ __device__ __forceinline__ float2 z_operator(const ZArgs &a, int o, int ix, int 
 // transform the two parts are separated with the partner at -kz,
 //   A = (C(kz) + conj C(-kz)) / 2,   B = (C(kz) - conj C(-kz)) / 2i,
 // each gets its own operator, and the results are repacked as A' + i B'.
-template <class Eng, int MODE>
-__global__ void __launch_bounds__(512) kw_zfused(ZArgs a) {
+template <class Eng, int MODE, int MAXT = 512>
+__global__ void __launch_bounds__(MAXT) kw_zfused(ZArgs a) {
     constexpr int E = Eng::E;
     extern __shared__ float2 sh[];
     const int tid = threadIdx.x;

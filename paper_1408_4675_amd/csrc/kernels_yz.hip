@@ -19,6 +19,19 @@ hipError_t launch_ypass(hipStream_t s, const GridDev &g, const LaunchCfg &c, con
     dim3 grid((g.M + a.tb - 1) / a.tb, g.nz, nfields);
     dim3 block(a.tb * a.plan.L);
     size_t lds = (size_t)a.tb * g.ny * sizeof(float2);
+    if (block.x > 512) {
+        // wide tiles: 1024-thread instantiations of the fixed engines
+        if (c.eng_y == ENG_F16) {
+            if (inverse) hipLaunchKernelGGL((kw_ypass<EngFixed<16>, true, 1024>), grid, block, lds, s, a);
+            else hipLaunchKernelGGL((kw_ypass<EngFixed<16>, false, 1024>), grid, block, lds, s, a);
+        } else if (c.eng_y == ENG_F8) {
+            if (inverse) hipLaunchKernelGGL((kw_ypass<EngFixed<8>, true, 1024>), grid, block, lds, s, a);
+            else hipLaunchKernelGGL((kw_ypass<EngFixed<8>, false, 1024>), grid, block, lds, s, a);
+        } else {
+            return hipErrorInvalidConfiguration;
+        }
+        return hipGetLastError();
+    }
     KW_ENGINE_SWITCH(c.eng_y, {
         if (inverse) hipLaunchKernelGGL((kw_ypass<Eng, true>), grid, block, lds, s, a);
         else hipLaunchKernelGGL((kw_ypass<Eng, false>), grid, block, lds, s, a);
@@ -51,13 +64,23 @@ hipError_t launch_zfused(hipStream_t s, const GridDev &g, const LaunchCfg &c, co
     dim3 grid = (mode == ZM_GRAD) ? dim3((nblk + 7) / 8 * 8 * 3, 1) : dim3(nblk, nout);
     dim3 block(a.tb * c.pz.L);
     size_t lds = (size_t)a.tb * g.nz * sizeof(float2);
-    KW_ENGINE_SWITCH(c.eng_z, {
-        if (mode == ZM_GRAD) hipLaunchKernelGGL((kw_zfused<Eng, ZM_GRAD>), grid, block, lds, s, a);
-        else if (mode == ZM_DIV) hipLaunchKernelGGL((kw_zfused<Eng, ZM_DIV>), grid, block, lds, s, a);
-        else if (mode == ZM_ABS) hipLaunchKernelGGL((kw_zfused<Eng, ZM_ABS>), grid, block, lds, s, a);
-        else if (mode == ZM_DIVT) hipLaunchKernelGGL((kw_zfused<Eng, ZM_DIVT>), grid, block, lds, s, a);
-        else hipLaunchKernelGGL((kw_zfused<Eng, ZM_GRADT>), grid, block, lds, s, a);
-    });
+#define KW_ZMODES(ENGT, MAXT)                                                                  \
+    do {                                                                                       \
+        if (mode == ZM_GRAD) hipLaunchKernelGGL((kw_zfused<ENGT, ZM_GRAD, MAXT>), grid, block, lds, s, a);   \
+        else if (mode == ZM_DIV) hipLaunchKernelGGL((kw_zfused<ENGT, ZM_DIV, MAXT>), grid, block, lds, s, a); \
+        else if (mode == ZM_ABS) hipLaunchKernelGGL((kw_zfused<ENGT, ZM_ABS, MAXT>), grid, block, lds, s, a); \
+        else if (mode == ZM_DIVT) hipLaunchKernelGGL((kw_zfused<ENGT, ZM_DIVT, MAXT>), grid, block, lds, s, a); \
+        else hipLaunchKernelGGL((kw_zfused<ENGT, ZM_GRADT, MAXT>), grid, block, lds, s, a);    \
+    } while (0)
+    if (block.x > 512) {
+        // wide tiles: 1024-thread instantiations of the fixed engines
+        if (c.eng_z == ENG_F16) KW_ZMODES(EngFixed<16>, 1024);
+        else if (c.eng_z == ENG_F8) KW_ZMODES(EngFixed<8>, 1024);
+        else return hipErrorInvalidConfiguration;
+        return hipGetLastError();
+    }
+    KW_ENGINE_SWITCH(c.eng_z, KW_ZMODES(Eng, 512));
+#undef KW_ZMODES
     return hipGetLastError();
 }
 

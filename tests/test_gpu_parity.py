@@ -280,8 +280,10 @@ def test_fft_engines_and_schedules_agree(kw):
         assert e < 1e-5
 
 
+# 1024-point y and z columns run in 1024-thread blocks of 16 columns; (40, 6,
+# 1024) and (40, 1024, 6) have a full and a ragged tile of 16 columns
 LONG = [(16, 8, 1024), (16, 1024, 8), (1024, 8, 8), (16, 8, 512), (32, 512, 6), (512, 6, 10),
-        (16, 8, 256), (24, 10, 960)]
+        (16, 8, 256), (24, 10, 960), (40, 6, 1024), (40, 1024, 6)]
 
 
 @pytest.mark.parametrize("shape", LONG, ids=["%dx%dx%d" % s for s in LONG])
