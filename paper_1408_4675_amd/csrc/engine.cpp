@@ -619,10 +619,7 @@ int pick_tiles(kw_sim *s, int tile_y, int tile_z) {
     const GridDev &g = s->g;
     // rows per block in the x kernels: about 256 threads
     c.tb_x = std::max(1, 256 / c.px.L);
-    auto x_lds_bytes = [&](int tb) {
-        return (size_t)tb * (g.M + (g.M >> 4) + 1) * sizeof(float2) + (size_t)tb * g.nx * sizeof(float);
-    };
-    while (c.tb_x > 1 && x_lds_bytes(c.tb_x) > 64 * 1024) c.tb_x /= 2;
+    while (c.tb_x > 1 && x_lds_bytes(g.M, g.nx, c.tb_x, true) > 64 * 1024) c.tb_x /= 2;
     // rows per block of the density kernel: as many as fit 512 threads and
     // 64 KB of LDS (measured: two blocks of ~8 wavefronts per CU beat smaller
     // blocks, and thread groups that straddle wavefronts cost little)
@@ -646,22 +643,20 @@ int pick_tiles(kw_sim *s, int tile_y, int tile_z) {
         const int max_threads = wide ? 1024 : 512;
         const size_t max_bytes = wide ? s->max_lds : (size_t)64 * 1024;
         int tb = 16;
-        while (tb > 1 && (tb * L > max_threads || (size_t)tb * n * sizeof(float2) > max_bytes))
-            tb /= 2;
+        while (tb > 1 && (tb * L > max_threads || col_lds_bytes(n, tb) > max_bytes)) tb /= 2;
         return tb;
     };
     c.tb_y = col_tile(g.ny, c.py.L, tile_y, c.eng_y == ENG_F8 || c.eng_y == ENG_F16);
     c.tb_z = col_tile(g.nz, c.pz.L, tile_z, c.eng_z == ENG_F8 || c.eng_z == ENG_F16);
-    const size_t xl = (size_t)c.tb_x * (g.M + (g.M >> 4) + 1) * sizeof(float2) +
-                      (size_t)c.tb_x * g.nx * sizeof(float);
     int rc;
-    if ((rc = check_tb("x pass", c.tb_x, c.px.L, xl)) != KW_OK) return rc;
+    if ((rc = check_tb("x pass", c.tb_x, c.px.L, x_lds_bytes(g.M, g.nx, c.tb_x, true))) != KW_OK)
+        return rc;
     const bool wide_y = c.eng_y == ENG_F8 || c.eng_y == ENG_F16;
     const bool wide_z = c.eng_z == ENG_F8 || c.eng_z == ENG_F16;
-    if ((rc = check_tb("y pass", c.tb_y, c.py.L, (size_t)c.tb_y * g.ny * sizeof(float2), wide_y,
+    if ((rc = check_tb("y pass", c.tb_y, c.py.L, col_lds_bytes(g.ny, c.tb_y), wide_y,
                        s->max_lds)) != KW_OK)
         return rc;
-    if ((rc = check_tb("z pass", c.tb_z, c.pz.L, (size_t)c.tb_z * g.nz * sizeof(float2), wide_z,
+    if ((rc = check_tb("z pass", c.tb_z, c.pz.L, col_lds_bytes(g.nz, c.tb_z), wide_z,
                        s->max_lds)) != KW_OK)
         return rc;
     return KW_OK;
@@ -1259,9 +1254,7 @@ int kw_set_plan(kw_sim *s, int axis, const int32_t *radices, int32_t n_radices, 
     int rc = pick_tiles(s, axis == 1 ? tile : s->cfg.tb_y, axis == 2 ? tile : s->cfg.tb_z);
     if (rc == KW_OK && axis == 0 && tile > 0) {
         s->cfg.tb_x = tile;
-        const size_t xl = (size_t)tile * (s->g.M + (s->g.M >> 4) + 1) * sizeof(float2) +
-                          (size_t)tile * s->g.nx * sizeof(float);
-        rc = check_tb("x pass", tile, s->cfg.px.L, xl);
+        rc = check_tb("x pass", tile, s->cfg.px.L, x_lds_bytes(s->g.M, s->g.nx, tile, true));
     }
     if (rc != KW_OK) {
         s->cfg = save;

@@ -110,6 +110,13 @@ __device__ __forceinline__ int col0_ky(int r, int ny) {
     return r - (ny - 1 - h);
 }
 
+// Twiddle tables are read from LDS inside the transforms: every kernel copies
+// the ones it needs to the start of its dynamic LDS first (a global read per
+// twiddle inside each pass put a memory latency on every pass).
+__device__ __forceinline__ void stage_table(float2 *dst, const float2 *__restrict__ src, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+}
+
 // Drive value s_e of element e in step n, at t = (n + 1/2) dt (the mass
 // source of Eq. (4d)): a_e sin(omega t + phi_e) = a_e cos(phi_e) sin(omega t)
 // + a_e sin(phi_e) cos(omega t) in float64, or the sampled signal.
@@ -140,7 +147,9 @@ struct YArgs {
 template <class Eng, bool INV, int MAXT = 512>
 __global__ void __launch_bounds__(MAXT) kw_ypass(YArgs a) {
     constexpr int E = Eng::E;
-    extern __shared__ float2 sh[];
+    extern __shared__ float2 lds_all[];
+    float2 *const tws = lds_all;             // ny twiddles
+    float2 *const sh = lds_all + a.ny;       // column tile
     const int tid = threadIdx.x;
     const int b = tid % a.tb, t = tid / a.tb;
     const int col = blockIdx.x * a.tb + b;
@@ -164,6 +173,8 @@ __global__ void __launch_bounds__(MAXT) kw_ypass(YArgs a) {
         for (int m = 0; m < E; ++m)
             if (m < cin) v[m] = base[(size_t)Eng::in_index(a.plan, t, m) * stride];
     }
+    stage_table(tws, a.tw, ny);
+    __syncthreads();
     const bool tile0 = blockIdx.x == 0;          // block-uniform
     if (INV && tile0) {
         // repack column 0: C(ky) = A(ky) + i B(ky), using A(-ky) = conj A(ky)
@@ -193,7 +204,7 @@ __global__ void __launch_bounds__(MAXT) kw_ypass(YArgs a) {
         }
         __syncthreads();
     }
-    Eng::template run<INV>(a.plan, a.tw, t, lds, v);
+    Eng::template run<INV>(a.plan, tws, t, lds, v);
     const int cout = Eng::out_count(a.plan, t);
     if (!INV && tile0) {
         // unpack column 0 into A (rows 1..h) and B (rows ny-h..ny-1)
@@ -279,7 +290,9 @@ __device__ __forceinline__ float2 z_operator(const ZArgs &a, int o, int ix, int 
 template <class Eng, int MODE, int MAXT = 512>
 __global__ void __launch_bounds__(MAXT) kw_zfused(ZArgs a) {
     constexpr int E = Eng::E;
-    extern __shared__ float2 sh[];
+    extern __shared__ float2 lds_all[];
+    float2 *const tws = lds_all;             // nz twiddles
+    float2 *const sh = lds_all + a.g.nz;     // column tile
     const int tid = threadIdx.x;
     const int b = tid % a.tb, t = tid / a.tb;
     const int ny = a.g.ny, M = a.g.M;
@@ -327,7 +340,9 @@ __global__ void __launch_bounds__(MAXT) kw_zfused(ZArgs a) {
         for (int m = 0; m < E; ++m)
             if (m < cin) v[m] = src[(size_t)Eng::in_index(a.pf, t, m) * stride];
     }
-    Eng::template run<false>(a.pf, a.t.tw_z, t, lds, v);
+    stage_table(tws, a.t.tw_z, a.g.nz);
+    __syncthreads();
+    Eng::template run<false>(a.pf, tws, t, lds, v);
     if (pairing && b == 0) {
         // the raw spectrum of the double row goes to LDS column 0 (free after
         // the transform's trailing barrier) for the pair loop below
@@ -370,7 +385,7 @@ __global__ void __launch_bounds__(MAXT) kw_zfused(ZArgs a) {
         }
         __syncthreads();
     }
-    Eng::template run<true>(a.pi, a.t.tw_z, t, lds, v);
+    Eng::template run<true>(a.pi, tws, t, lds, v);
     if (ok) {
         float2 *dst = pick3(a.out, o) + off;
 #pragma unroll
@@ -406,10 +421,10 @@ struct XArgs {
 template <class Eng>
 __device__ __forceinline__ void row_c2r(const XArgs &a, const float2 *__restrict__ row, bool ok,
                                         int t, const RowLds &lds, float2 (&v)[Eng::E],
-                                        int salt = 0) {
+                                        const float2 *twx, const float2 *twp, int salt = 0) {
     constexpr int E = Eng::E;
     const int M = a.g.M;
-    const float2 *tw_post = a.t.tw_post + salt;
+    const float2 *tw_post = twp + salt;
     const int cin = Eng::in_count(a.pi, t);
     if (ok) {
 #pragma unroll
@@ -432,17 +447,18 @@ __device__ __forceinline__ void row_c2r(const XArgs &a, const float2 *__restrict
             }
         }
     }
-    Eng::template run<true>(a.pi, a.t.tw_x + salt, t, lds, v);
+    Eng::template run<true>(a.pi, twx + salt, t, lds, v);
 }
 
 // r2c: v[m] = x[2n] + i x[2n+1], n = in_index(pf, t, m)  ->  packed spectrum row
 template <class Eng>
 __device__ __forceinline__ void row_r2c(const XArgs &a, float2 *__restrict__ row, bool ok, int t,
-                                        const RowLds &lds, float2 (&v)[Eng::E], int salt = 0) {
+                                        const RowLds &lds, float2 (&v)[Eng::E],
+                                        const float2 *twx, const float2 *twp, int salt = 0) {
     constexpr int E = Eng::E;
     const int M = a.g.M;
-    const float2 *tw_post = a.t.tw_post + salt;
-    Eng::template run<false>(a.pf, a.t.tw_x + salt, t, lds, v);
+    const float2 *tw_post = twp + salt;
+    Eng::template run<false>(a.pf, twx + salt, t, lds, v);
     const int cout = Eng::out_count(a.pf, t);
 #pragma unroll
     for (int m = 0; m < E; ++m)
@@ -473,7 +489,12 @@ __device__ __forceinline__ void row_r2c(const XArgs &a, float2 *__restrict__ row
 
 #define KW_XPROLOGUE                                                   \
     constexpr int E = Eng::E;                                          \
-    extern __shared__ float2 sh[];                                     \
+    extern __shared__ float2 lds_all[];                                \
+    float2 *const tws = lds_all;          /* tw_x, then tw_post */     \
+    float2 *const sh = lds_all + 2 * a.g.M;                            \
+    stage_table(tws, a.t.tw_x, a.g.M);                                 \
+    stage_table(tws + a.g.M, a.t.tw_post, a.g.M);                      \
+    __syncthreads();                                                   \
     const int L = a.pf.L;                                              \
     const int tid = threadIdx.x, t = tid % L, b = tid / L;             \
     const int row = blockIdx.x * a.tb + b;                             \
@@ -492,7 +513,7 @@ __global__ void __launch_bounds__(512) kw_xvel(XArgs a) {
     const int iy = rr % a.g.ny, iz = rr / a.g.ny;
     const int xi = blockIdx.y;
     float2 v[E];
-    row_c2r<Eng>(a, pick3(a.Sin, xi) + (size_t)rr * M, ok, t, lds, v);
+    row_c2r<Eng>(a, pick3(a.Sin, xi) + (size_t)rr * M, ok, t, lds, v, tws, tws + M);
     if (ok) {
         float *u = pick3(a.fld, xi);
         const Coef dtr = xi == 0 ? a.m.dtr[0] : xi == 1 ? a.m.dtr[1] : a.m.dtr[2];
@@ -517,7 +538,7 @@ __global__ void __launch_bounds__(512) kw_xvel(XArgs a) {
             }
         }
     }
-    row_r2c<Eng>(a, pick3(a.Sout, xi) + (size_t)rr * M, ok, t, lds, v);
+    row_r2c<Eng>(a, pick3(a.Sout, xi) + (size_t)rr * M, ok, t, lds, v, tws, tws + M);
 }
 
 // Source values of the rows of this block, scattered into a per-row LDS line
@@ -588,7 +609,8 @@ __device__ __forceinline__ void record_mask(const XArgs &a, float *line, int row
 template <class Eng, bool MASK = true>
 __device__ __forceinline__ void finish_pressure(const XArgs &a, float *line, int row, bool ok,
                                                 int t, int L, int b, const RowLds &lds,
-                                                float2 (&v)[Eng::E]) {
+                                                float2 (&v)[Eng::E], const float2 *twx,
+                                                const float2 *twp) {
     constexpr int E = Eng::E;
     const int M = a.g.M, nx = a.g.nx;
     const size_t rbase = (size_t)(ok ? row : 0) * nx;
@@ -621,7 +643,7 @@ __device__ __forceinline__ void finish_pressure(const XArgs &a, float *line, int
         if (rec && !a.sen.all_points && a.sen.row_ptr)
             record_mask<Eng>(a, line, row, ok, t, L, b, step, v);
     }
-    row_r2c<Eng>(a, a.Sout[0] + (size_t)(ok ? row : 0) * M, ok, t, lds, v);
+    row_r2c<Eng>(a, a.Sout[0] + (size_t)(ok ? row : 0) * M, ok, t, lds, v, twx, twp);
 }
 
 // Density update.  The three split components are coupled only through
@@ -634,14 +656,16 @@ __device__ __forceinline__ void finish_pressure(const XArgs &a, float *line, int
 // The groups exchange only what the others need: group 0 keeps du_0 and group
 // 1 keeps rho_1 in registers; rho_0, du_1 and rho_2 go to the (then idle) FFT
 // buffers of groups 0, 1 and 2, and du_2 to a line of its own.
-// LDS: [3 groups][tb rows] FFT buffers, [tb] du_2 lines, [tb] source lines.
+// LDS: [3 groups][tb rows] FFT buffers, [tb] du_2 lines (twiddles during the transforms),
+// [tb] source lines.
 // ABS (= a.m.absorbing) is a template parameter: the lossless tail (equation
 // of state, sensors, pressure transform) would otherwise set the register
 // count of the absorbing kernel too.
 template <class Eng, bool ABS>
 __global__ void __launch_bounds__(512) kw_xden(XArgs a) {
     constexpr int E = Eng::E;
-    extern __shared__ float2 sh[];
+    extern __shared__ float2 lds_all[];
+    float2 *const sh = lds_all;
     const int L = a.pf.L;
     const int M = a.g.M, nx = a.g.nx, tb = a.tb;
     const int tid = threadIdx.x;
@@ -660,6 +684,14 @@ __global__ void __launch_bounds__(512) kw_xden(XArgs a) {
     float2 *buf2 = sh + (size_t)(2 * tb + b) * RP;
     float2 *du2 = sh + (size_t)3 * tb * RP + (size_t)b * M;   // nx floats per row
     float *line = reinterpret_cast<float *>(sh + (size_t)3 * tb * RP + (size_t)tb * M);
+    // The transform twiddles (tw_x) are staged in the du_2 lines, which are
+    // free during both transforms: once for the inverse transforms of phase 1
+    // (du_2 is written after them) and again for the forward transforms of
+    // phase 2 (after du_2 has been read).  tw_post, read once per element
+    // outside the passes, stays in global memory.  This keeps the LDS of three
+    // 10-row blocks within a CU.
+    float2 *const tws = sh + (size_t)3 * tb * RP;
+    stage_table(tws, a.t.tw_x, M);
     const float dt = a.g.dt;
     const int cupd = Eng::out_count(a.pi, t);
 
@@ -669,7 +701,7 @@ __global__ void __launch_bounds__(512) kw_xden(XArgs a) {
     // phase 1: component g (row_c2r ends with a barrier, so the FFT buffers
     // are free for the exchange afterwards)
     float2 v[E];
-    row_c2r<Eng>(a, pick3(a.Sin, g) + (size_t)rr * M, ok, t, lds, v);
+    row_c2r<Eng>(a, pick3(a.Sin, g) + (size_t)rr * M, ok, t, lds, v, tws, a.t.tw_post);
     {
         float *rho = pick3(a.fld, g);
         const float qy = a.t.pml_y[iy], qz = a.t.pml_z[iz];
@@ -744,23 +776,27 @@ __global__ void __launch_bounds__(512) kw_xden(XArgs a) {
         }
     }
     __syncthreads();   // the forward transforms below overwrite the exchanged values
+    stage_table(tws, a.t.tw_x, M);
+    __syncthreads();
     if constexpr (ABS) {
         float2 *dst = (g == 0) ? a.Sout[0] : a.Sout[1];
-        row_r2c<Eng>(a, dst + (size_t)rr * M, ok && g < 2, t, lds, v);
+        row_r2c<Eng>(a, dst + (size_t)rr * M, ok && g < 2, t, lds, v, tws, a.t.tw_post);
     } else {
-        finish_pressure<Eng>(a, line, rr, ok && g == 1, t, L, b, lds, v);
+        finish_pressure<Eng>(a, line, rr, ok && g == 1, t, L, b, lds, v, tws, a.t.tw_post);
     }
 }
 
 // MASK: mask sensors are recorded (their row scan is compiled in only then,
 // which keeps the register count of the all-points and no-sensor cases lower)
+// Asked to fit six wavefronts per SIMD (80 registers; a few bytes spill):
+// measured faster than five without spills.
 template <class Eng, bool MASK>
-__global__ void __launch_bounds__(512) kw_xeos(XArgs a) {
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6))) kw_xeos(XArgs a) {
     KW_XPROLOGUE
     float *line = reinterpret_cast<float *>(sh + (size_t)a.tb * row_pitch(M));
     float2 va[E], v[E];
-    row_c2r<Eng>(a, a.Sin[0] + (size_t)rr * M, ok, t, lds, va);
-    row_c2r<Eng>(a, a.Sin[1] + (size_t)rr * M, ok, t, lds, v);
+    row_c2r<Eng>(a, a.Sin[0] + (size_t)rr * M, ok, t, lds, va, tws, tws + M);
+    row_c2r<Eng>(a, a.Sin[1] + (size_t)rr * M, ok, t, lds, v, tws, tws + M);
     if (ok) {
 #pragma unroll
         for (int m = 0; m < E; ++m) {
@@ -782,7 +818,7 @@ __global__ void __launch_bounds__(512) kw_xeos(XArgs a) {
             }
         }
     }
-    finish_pressure<Eng, MASK>(a, line, rr, ok, t, L, b, lds, v);
+    finish_pressure<Eng, MASK>(a, line, rr, ok, t, L, b, lds, v, tws, tws + M);
 }
 
 template <class Eng>
@@ -795,14 +831,14 @@ __global__ void __launch_bounds__(512) kw_xfwd(XArgs a) {
         for (int m = 0; m < E; ++m)
             if (m < cin) v[m] = ld2(a.rsrc, rbase + 2 * Eng::in_index(a.pf, t, m));
     }
-    row_r2c<Eng>(a, a.Sout[0] + (size_t)rr * M, ok, t, lds, v);
+    row_r2c<Eng>(a, a.Sout[0] + (size_t)rr * M, ok, t, lds, v, tws, tws + M);
 }
 
 template <class Eng>
 __global__ void __launch_bounds__(512) kw_xinv(XArgs a) {
     KW_XPROLOGUE
     float2 v[E];
-    row_c2r<Eng>(a, a.Sin[0] + (size_t)rr * M, ok, t, lds, v);
+    row_c2r<Eng>(a, a.Sin[0] + (size_t)rr * M, ok, t, lds, v, tws, tws + M);
     if (ok) {
 #pragma unroll
         for (int m = 0; m < E; ++m)

@@ -13,9 +13,7 @@ static XArgs make_xargs(const GridDev &g, const LaunchCfg &c, const Tables &t) {
     return a;
 }
 static inline size_t x_lds(const GridDev &g, const LaunchCfg &c, bool line) {
-    size_t n = (size_t)c.tb_x * row_pitch(g.M) * sizeof(float2);
-    if (line) n += (size_t)c.tb_x * g.nx * sizeof(float);
-    return n;
+    return x_lds_bytes(g.M, g.nx, c.tb_x, line);
 }
 #define KW_XLAUNCH(KERNEL, LINE) KW_XLAUNCH_N(KERNEL, LINE, 1)
 #define KW_XLAUNCH_N(KERNEL, LINE, NY)                                               \

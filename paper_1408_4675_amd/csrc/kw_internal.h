@@ -145,8 +145,17 @@ inline bool den_needs_line(const Medium &m, const SourceDev &src, const SensorDe
 }
 inline size_t den_lds_bytes(int M, int nx, int tb, bool line) {
     const size_t rp = (size_t)M + (M >> 4) + 1;
-    return (size_t)3 * tb * rp * 8 + (size_t)tb * M * 8 + (line ? (size_t)tb * nx * 4 : 0);
+    return (size_t)3 * tb * rp * 8 + (size_t)tb * M * 8 +
+           (line ? (size_t)tb * nx * 4 : 0);
 }
+// LDS of the other x kernels (twiddle tables, one FFT row buffer per row, and
+// optionally a line of nx floats per row), of the y pass and of the z pass
+// (twiddle table and the column tile)
+inline size_t x_lds_bytes(int M, int nx, int tb, bool line) {
+    const size_t rp = (size_t)M + (M >> 4) + 1;
+    return (size_t)2 * M * 8 + (size_t)tb * rp * 8 + (line ? (size_t)tb * nx * 4 : 0);
+}
+inline size_t col_lds_bytes(int n, int tb) { return (size_t)n * 8 + (size_t)tb * n * 8; }
 
 // GRAD: one input, output o multiplied by D+_o kappa / N          (Eq. (4a))
 // DIV:  input o, output o multiplied by D-_o kappa / N            (Eq. (4c))
