@@ -638,16 +638,16 @@ int pick_tiles(kw_sim *s, int tile_y, int tile_z) {
     // where a block can hold them -- for the fixed engines up to 1024 threads
     // and the device's LDS per block (measured at 1024^3: 120 -> 111 ms per
     // step against 8 columns of 512 threads), else 512 threads and 64 KB
-    auto col_tile = [&](int n, int L, int req, bool wide) {
+    auto col_tile = [&](int n, int L, int req, bool wide, size_t (*bytes)(int, int)) {
         if (req > 0) return req;
         const int max_threads = wide ? 1024 : 512;
         const size_t max_bytes = wide ? s->max_lds : (size_t)64 * 1024;
         int tb = 16;
-        while (tb > 1 && (tb * L > max_threads || col_lds_bytes(n, tb) > max_bytes)) tb /= 2;
+        while (tb > 1 && (tb * L > max_threads || bytes(n, tb) > max_bytes)) tb /= 2;
         return tb;
     };
-    c.tb_y = col_tile(g.ny, c.py.L, tile_y, c.eng_y == ENG_F8 || c.eng_y == ENG_F16);
-    c.tb_z = col_tile(g.nz, c.pz.L, tile_z, c.eng_z == ENG_F8 || c.eng_z == ENG_F16);
+    c.tb_y = col_tile(g.ny, c.py.L, tile_y, c.eng_y == ENG_F8 || c.eng_y == ENG_F16, col_lds_bytes);
+    c.tb_z = col_tile(g.nz, c.pz.L, tile_z, c.eng_z == ENG_F8 || c.eng_z == ENG_F16, zcol_lds_bytes);
     int rc;
     if ((rc = check_tb("x pass", c.tb_x, c.px.L, x_lds_bytes(g.M, g.nx, c.tb_x, true))) != KW_OK)
         return rc;
@@ -656,7 +656,7 @@ int pick_tiles(kw_sim *s, int tile_y, int tile_z) {
     if ((rc = check_tb("y pass", c.tb_y, c.py.L, col_lds_bytes(g.ny, c.tb_y), wide_y,
                        s->max_lds)) != KW_OK)
         return rc;
-    if ((rc = check_tb("z pass", c.tb_z, c.pz.L, col_lds_bytes(g.nz, c.tb_z), wide_z,
+    if ((rc = check_tb("z pass", c.tb_z, c.pz.L, zcol_lds_bytes(g.nz, c.tb_z), wide_z,
                        s->max_lds)) != KW_OK)
         return rc;
     return KW_OK;

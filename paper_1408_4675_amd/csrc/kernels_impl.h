@@ -260,9 +260,11 @@ struct ZArgs {
 };
 
 // multiplier of output o at (kx index ix (M = Nyquist), ky index iy, kz index iz)
+// kzl, dzl: kz and the z factor D+-_z of the mode, staged in LDS
 template <int MODE>
-__device__ __forceinline__ float2 z_operator(const ZArgs &a, int o, int ix, int iy, int iz) {
-    const float kx = a.t.kx[ix], ky = a.t.ky[iy], kz = a.t.kz[iz];
+__device__ __forceinline__ float2 z_operator(const ZArgs &a, int o, int ix, int iy, int iz,
+                                             const float *kzl, const float2 *dzl) {
+    const float kx = a.t.kx[ix], ky = a.t.ky[iy], kz = kzl[iz];
     const float k2 = kx * kx + ky * ky + kz * kz;
     if constexpr (MODE == ZM_ABS) {
         if (k2 <= 0.0f) return make_float2(0.0f, 0.0f);
@@ -272,9 +274,9 @@ __device__ __forceinline__ float2 z_operator(const ZArgs &a, int o, int ix, int 
         const float s = kappa_of_x2(a.g.half_cdt * a.g.half_cdt * k2) * a.g.inv_n;
         float2 d;
         if (MODE == ZM_GRAD || MODE == ZM_GRADT)
-            d = (o == 0) ? a.t.dpx[ix] : (o == 1) ? a.t.dpy[iy] : a.t.dpz[iz];
+            d = (o == 0) ? a.t.dpx[ix] : (o == 1) ? a.t.dpy[iy] : dzl[iz];
         else
-            d = (o == 0) ? a.t.dmx[ix] : (o == 1) ? a.t.dmy[iy] : a.t.dmz[iz];
+            d = (o == 0) ? a.t.dmx[ix] : (o == 1) ? a.t.dmy[iy] : dzl[iz];
         if constexpr (MODE == ZM_DIVT || MODE == ZM_GRADT) d = c_conj(d);
         return c_scale(d, s);
     }
@@ -290,9 +292,12 @@ __device__ __forceinline__ float2 z_operator(const ZArgs &a, int o, int ix, int 
 template <class Eng, int MODE, int MAXT = 512>
 __global__ void __launch_bounds__(MAXT) kw_zfused(ZArgs a) {
     constexpr int E = Eng::E;
+    // LDS: nz twiddles, nz z factors, nz wavenumbers kz, then the column tile
     extern __shared__ float2 lds_all[];
-    float2 *const tws = lds_all;             // nz twiddles
-    float2 *const sh = lds_all + a.g.nz;     // column tile
+    float2 *const tws = lds_all;
+    float2 *const dzl = lds_all + a.g.nz;
+    float *const kzl = reinterpret_cast<float *>(lds_all + 2 * a.g.nz);
+    float2 *const sh = lds_all + zpass_table_slots(a.g.nz);
     const int tid = threadIdx.x;
     const int b = tid % a.tb, t = tid / a.tb;
     const int ny = a.g.ny, M = a.g.M;
@@ -341,6 +346,9 @@ __global__ void __launch_bounds__(MAXT) kw_zfused(ZArgs a) {
             if (m < cin) v[m] = src[(size_t)Eng::in_index(a.pf, t, m) * stride];
     }
     stage_table(tws, a.t.tw_z, a.g.nz);
+    if constexpr (MODE != ZM_ABS)
+        stage_table(dzl, (MODE == ZM_GRAD || MODE == ZM_GRADT) ? a.t.dpz : a.t.dmz, a.g.nz);
+    for (int i = threadIdx.x; i < a.g.nz; i += blockDim.x) kzl[i] = a.t.kz[i];
     __syncthreads();
     Eng::template run<false>(a.pf, tws, t, lds, v);
     if (pairing && b == 0) {
@@ -353,7 +361,7 @@ __global__ void __launch_bounds__(MAXT) kw_zfused(ZArgs a) {
 #pragma unroll
     for (int m = 0; m < E; ++m)
         if (m < cmid)
-            v[m] = c_mul(v[m], z_operator<MODE>(a, o, ix, iyk, Eng::out_index(a.pf, t, m)));
+            v[m] = c_mul(v[m], z_operator<MODE>(a, o, ix, iyk, Eng::out_index(a.pf, t, m), kzl, dzl));
     if (pairing) {
         // (kz, -kz) pairs of the double row, one pair per iteration and thread,
         // updated in place in LDS (a pair is read and written by one thread)
@@ -366,13 +374,13 @@ __global__ void __launch_bounds__(MAXT) kw_zfused(ZArgs a) {
                 // A(kz) = (C(kz) + conj C(-kz)) / 2, B(kz) = (C(kz) - conj C(-kz)) / 2i
                 const float2 s1 = c_add(c1, c_conj(c2)), d1 = c_sub(c1, c_conj(c2));
                 const float2 A1 = c_scale(s1, 0.5f), B1 = make_float2(0.5f * d1.y, -0.5f * d1.x);
-                const float2 ya = c_mul(A1, z_operator<MODE>(a, o, 0, iy, iz));
-                const float2 yb = c_mul(B1, z_operator<MODE>(a, o, M, iy, iz));
+                const float2 ya = c_mul(A1, z_operator<MODE>(a, o, 0, iy, iz, kzl, dzl));
+                const float2 yb = c_mul(B1, z_operator<MODE>(a, o, M, iy, iz, kzl, dzl));
                 lds.st(iz, make_float2(ya.x - yb.y, ya.y + yb.x));          // ya + i yb
                 if (jz != iz) {
                     // A(-kz) = conj A(kz), B(-kz) = conj B(kz)
-                    const float2 za = c_mul(c_conj(A1), z_operator<MODE>(a, o, 0, iy, jz));
-                    const float2 zb = c_mul(c_conj(B1), z_operator<MODE>(a, o, M, iy, jz));
+                    const float2 za = c_mul(c_conj(A1), z_operator<MODE>(a, o, 0, iy, jz, kzl, dzl));
+                    const float2 zb = c_mul(c_conj(B1), z_operator<MODE>(a, o, M, iy, jz, kzl, dzl));
                     lds.st(jz, make_float2(za.x - zb.y, za.y + zb.x));
                 }
             }

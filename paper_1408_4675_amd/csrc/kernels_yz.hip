@@ -63,7 +63,7 @@ hipError_t launch_zfused(hipStream_t s, const GridDev &g, const LaunchCfg &c, co
     // gradient: 1D grid, XCD-aware order (see kw_zfused), padded to whole groups of 8 tiles
     dim3 grid = (mode == ZM_GRAD) ? dim3((nblk + 7) / 8 * 8 * 3, 1) : dim3(nblk, nout);
     dim3 block(a.tb * c.pz.L);
-    size_t lds = col_lds_bytes(g.nz, a.tb);
+    size_t lds = zcol_lds_bytes(g.nz, a.tb);
 #define KW_ZMODES(ENGT, MAXT)                                                                  \
     do {                                                                                       \
         if (mode == ZM_GRAD) hipLaunchKernelGGL((kw_zfused<ENGT, ZM_GRAD, MAXT>), grid, block, lds, s, a);   \

@@ -156,6 +156,11 @@ inline size_t x_lds_bytes(int M, int nx, int tb, bool line) {
     return (size_t)2 * M * 8 + (size_t)tb * rp * 8 + (line ? (size_t)tb * nx * 4 : 0);
 }
 inline size_t col_lds_bytes(int n, int tb) { return (size_t)n * 8 + (size_t)tb * n * 8; }
+// the z pass keeps three tables of nz entries (twiddles, z factors, kz) before its tile
+__host__ __device__ inline int zpass_table_slots(int nz) { return 2 * nz + (nz + 1) / 2; }
+inline size_t zcol_lds_bytes(int n, int tb) {
+    return (size_t)zpass_table_slots(n) * 8 + (size_t)tb * n * 8;
+}
 
 // GRAD: one input, output o multiplied by D+_o kappa / N          (Eq. (4a))
 // DIV:  input o, output o multiplied by D-_o kappa / N            (Eq. (4c))
