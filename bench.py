@@ -318,7 +318,8 @@ def main():
             out["large"] = dict(error=str(e))
     if not args.no_cpu:
         log("timing the CPU oracle baseline")
-        out["cpu_baseline"] = cpu_baseline(sc.tissue_bowl(seed=0, n=256, steps=3))
+        # about 12 s of FP64 work on a 16-core host (1.4 s per step)
+        out["cpu_baseline"] = cpu_baseline(sc.tissue_bowl(seed=0, n=256, steps=9), warm=1, steps=8)
     print(json.dumps(out), flush=True)
 
 

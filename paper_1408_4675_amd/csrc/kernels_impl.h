@@ -692,14 +692,16 @@ __global__ void __launch_bounds__(512) kw_xden(XArgs a) {
     float2 *buf2 = sh + (size_t)(2 * tb + b) * RP;
     float2 *du2 = sh + (size_t)3 * tb * RP + (size_t)b * M;   // nx floats per row
     float *line = reinterpret_cast<float *>(sh + (size_t)3 * tb * RP + (size_t)tb * M);
-    // The transform twiddles (tw_x) are staged in the du_2 lines, which are
-    // free during both transforms: once for the inverse transforms of phase 1
-    // (du_2 is written after them) and again for the forward transforms of
-    // phase 2 (after du_2 has been read).  tw_post, read once per element
-    // outside the passes, stays in global memory.  This keeps the LDS of three
-    // 10-row blocks within a CU.
+    // The twiddle tables (tw_x, and tw_post when there are two lines or more)
+    // are staged in the du_2 lines, which are free during both transforms:
+    // once for the inverse transforms of phase 1 (du_2 is written after them)
+    // and again for the forward transforms of phase 2 (after du_2 has been
+    // read).  This keeps the LDS of three 10-row blocks within a CU.
     float2 *const tws = sh + (size_t)3 * tb * RP;
+    const bool post_lds = tb >= 2;                                    // block-uniform
+    const float2 *const twp = post_lds ? tws + M : a.t.tw_post;
     stage_table(tws, a.t.tw_x, M);
+    if (post_lds) stage_table(tws + M, a.t.tw_post, M);
     const float dt = a.g.dt;
     const int cupd = Eng::out_count(a.pi, t);
 
@@ -709,7 +711,7 @@ __global__ void __launch_bounds__(512) kw_xden(XArgs a) {
     // phase 1: component g (row_c2r ends with a barrier, so the FFT buffers
     // are free for the exchange afterwards)
     float2 v[E];
-    row_c2r<Eng>(a, pick3(a.Sin, g) + (size_t)rr * M, ok, t, lds, v, tws, a.t.tw_post);
+    row_c2r<Eng>(a, pick3(a.Sin, g) + (size_t)rr * M, ok, t, lds, v, tws, twp);
     {
         float *rho = pick3(a.fld, g);
         const float qy = a.t.pml_y[iy], qz = a.t.pml_z[iz];
@@ -785,12 +787,13 @@ __global__ void __launch_bounds__(512) kw_xden(XArgs a) {
     }
     __syncthreads();   // the forward transforms below overwrite the exchanged values
     stage_table(tws, a.t.tw_x, M);
+    if (post_lds) stage_table(tws + M, a.t.tw_post, M);
     __syncthreads();
     if constexpr (ABS) {
         float2 *dst = (g == 0) ? a.Sout[0] : a.Sout[1];
-        row_r2c<Eng>(a, dst + (size_t)rr * M, ok && g < 2, t, lds, v, tws, a.t.tw_post);
+        row_r2c<Eng>(a, dst + (size_t)rr * M, ok && g < 2, t, lds, v, tws, twp);
     } else {
-        finish_pressure<Eng>(a, line, rr, ok && g == 1, t, L, b, lds, v, tws, a.t.tw_post);
+        finish_pressure<Eng>(a, line, rr, ok && g == 1, t, L, b, lds, v, tws, twp);
     }
 }
 

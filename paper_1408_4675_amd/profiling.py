@@ -23,6 +23,7 @@ import glob
 import hashlib
 import json
 import os
+import re
 import sys
 from typing import Dict, List, Optional
 
@@ -49,13 +50,13 @@ def kernel_source_hash() -> str:
 
 def kernel_class(name: str) -> Optional[str]:
     """Class of a demangled kernel name (None for kernels of other code)."""
-    if "kw_ypass" in name:
-        return "ypass_inv" if "true>" in name else "ypass_fwd"
-    if "kw_zfused" in name:
-        for mode, cls in ((", 0>", "zfused_grad"), (", 1>", "zfused_div"), (", 2>", "zfused_abs")):
-            if mode in name:
-                return cls
-        return "zfused"
+    m = re.search(r"kw_ypass<.*?, (true|false)(, \d+)?>", name)
+    if m:
+        return "ypass_inv" if m.group(1) == "true" else "ypass_fwd"
+    m = re.search(r"kw_zfused<.*?>, (\d)(, \d+)?>", name)
+    if m:
+        return {"0": "zfused_grad", "1": "zfused_div", "2": "zfused_abs",
+                "3": "zfused_divt", "4": "zfused_gradt"}.get(m.group(1), "zfused")
     for frag, cls in CLASS_OF:
         if cls and frag in name:
             return cls
