@@ -59,6 +59,12 @@ extern "C" {
 #define KW_REC_P_FINAL   8u  /* p on the whole grid after the last step                */
 #define KW_REC_U_FINAL  16u  /* ux, uy, uz (staggered) after the last step, 3 fields   */
 #define KW_REC_INTENSITY 32u /* time-mean p^2 / (rho0 c0) at the sensor points         */
+#define KW_REC_P_MIN     64u /* running minimum of p (peak negative pressure)          */
+#define KW_REC_HARMONICS 128u /* complex amplitudes of harmonics 1..n_harmonics of
+                                harmonic_freq: A_h = (2/N) sum_m p^m e^{-i h 2 pi f m dt}
+                                over the N recorded steps m, per sensor point          */
+#define KW_REC_U_SERIES  256u /* u_x, u_y, u_z (staggered) at the sensor points, one
+                                row of 3 x points per recorded step (mask sensor only) */
 
 /* fields for kw_set_field / kw_gather_field (whole grid, float32) */
 #define KW_FIELD_P       1   /* acoustic pressure p^n                                  */
@@ -114,13 +120,19 @@ typedef struct kw_source {
 
 /* Sensor: quantities in `record` are kept for the points in `index` (strictly
  * increasing) or for every grid point when index == NULL (n_points ignored).
- * The pressure p^(n) after step n is recorded when n >= record_start (>= 1). */
+ * The pressure p^(n) after step n is recorded when n >= record_start (>= 1),
+ * and with it u^(n-1/2) for KW_REC_U_SERIES.  The paper's application keeps
+ * peak positive and negative pressure over the domain and the time-varying
+ * pressure and velocity over a region (Section 5); the harmonic amplitudes are
+ * an on-device reduction of that time series. */
 typedef struct kw_sensor {
     uint32_t       record;
     int64_t        n_points;
     const int64_t *index;
     int32_t        record_start;
-    int32_t        series_capacity;   /* rows kept for KW_REC_P_SERIES */
+    int32_t        series_capacity;   /* rows kept for KW_REC_P_SERIES / KW_REC_U_SERIES */
+    int32_t        n_harmonics;       /* 1..16 with KW_REC_HARMONICS                       */
+    double         harmonic_freq;     /* [Hz]; 0 -> the source frequency                  */
 } kw_sensor;
 
 typedef struct kw_stats_t {
@@ -157,8 +169,10 @@ int kw_create(const kw_grid *grid, const kw_medium *medium, const kw_source *sou
 int kw_step(kw_sim *sim, int32_t n);
 
 /* Copy a recorded quantity (one KW_REC_* bit) into dst, as float32:
- *   P_MAX, P_RMS, INTENSITY: one value per sensor point (or grid point);
+ *   P_MAX, P_MIN, P_RMS, INTENSITY: one value per sensor point (or grid point);
  *   P_SERIES: rows x sensor points, rows = min(recorded steps, capacity);
+ *   U_SERIES: rows x 3 x sensor points;
+ *   HARMONICS: n_harmonics x points x 2 (real, imaginary);
  *   P_FINAL: nx*ny*nz values; U_FINAL: 3*nx*ny*nz values (ux, uy, uz).
  * dst is device memory when dst_is_device != 0, else host memory.  The call
  * synchronizes the stream; it fails with KW_EINVAL when dst_bytes is too

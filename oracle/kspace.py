@@ -194,9 +194,18 @@ class Oracle:
         self.record_start = int(sen.record_start)
         nrec = self.N if self.sensor_index is None else self.sensor_index.size
         self.p_max = np.full(nrec, -np.inf)
+        self.p_min = np.full(nrec, np.inf)
         self.p_sum2 = np.zeros(nrec)
         self.n_rec = 0
         self.series = []
+        self.u_series = []
+        # harmonic sums: sum over recorded m of p^m exp(-i h w m dt), h = 1..H
+        self.n_harm = int(getattr(sen, "n_harmonics", 0) or 0)
+        f = float(getattr(sen, "harmonic_freq", 0.0) or 0.0)
+        if f <= 0.0 and scen.source is not None:
+            f = float(scen.source.freq)
+        self.harm_freq = f
+        self.harm = np.zeros((self.n_harm, nrec), np.complex128)
         self.fft_forward = 0
         self.fft_inverse = 0
 
@@ -298,10 +307,16 @@ class Oracle:
         flat = self.p.reshape(-1)
         v = flat if self.sensor_index is None else flat[self.sensor_index]
         self.p_max = np.maximum(self.p_max, v)
+        self.p_min = np.minimum(self.p_min, v)
         self.p_sum2 += v * v
         self.n_rec += 1
         if self.sensor_index is not None:
             self.series.append(v.copy())
+            # u^(n-1/2) is recorded together with p^n
+            self.u_series.append(np.stack([u.reshape(-1)[self.sensor_index] for u in self.u]))
+        t = self.n * self.dt
+        for h in range(self.n_harm):
+            self.harm[h] += v * np.exp(-1j * (h + 1) * 2.0 * np.pi * self.harm_freq * t)
 
     # -- outputs ---------------------------------------------------------------
     @property
@@ -310,6 +325,14 @@ class Oracle:
 
     def p_series(self) -> np.ndarray:
         return np.array(self.series) if self.series else np.zeros((0, 0))
+
+    def u_series_array(self) -> np.ndarray:
+        """[recorded steps, 3, sensor points]."""
+        return np.array(self.u_series) if self.u_series else np.zeros((0, 3, 0))
+
+    def harmonics(self) -> np.ndarray:
+        """Complex amplitudes A_h = (2/N) sum_m p^m exp(-i h w t_m), [H, points]."""
+        return 2.0 * self.harm / max(self.n_rec, 1)
 
     def intensity(self) -> np.ndarray:
         """Time-mean of p^2 / (rho0 c0) over the recorded steps."""

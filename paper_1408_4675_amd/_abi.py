@@ -27,6 +27,9 @@ KW_REC_P_SERIES = 4
 KW_REC_P_FINAL = 8
 KW_REC_U_FINAL = 16
 KW_REC_INTENSITY = 32
+KW_REC_P_MIN = 64
+KW_REC_HARMONICS = 128
+KW_REC_U_SERIES = 256
 
 KW_FIELD_P = 1
 KW_FIELD_UX = 2
@@ -70,7 +73,8 @@ class KwSource(C.Structure):
 class KwSensor(C.Structure):
     _fields_ = [("record", C.c_uint32), ("n_points", C.c_int64),
                 ("index", C.POINTER(C.c_int64)), ("record_start", C.c_int32),
-                ("series_capacity", C.c_int32)]
+                ("series_capacity", C.c_int32), ("n_harmonics", C.c_int32),
+                ("harmonic_freq", C.c_double)]
 
 
 class KwStats(C.Structure):

@@ -214,7 +214,7 @@ struct Layout {
     size_t tw_x, tw_post, tw_y, tw_z, kx, ky, kz, dpx, dmx, dpy, dmy, dpz, dmz;
     size_t pml[6];
     size_t src_row, src_x, src_e, src_c, src_ac, src_as, src_sig;
-    size_t sen_row, sen_x, sen_id, sen_idx, p_max, p_sum2, series;
+    size_t sen_row, sen_x, sen_id, sen_idx, p_max, p_sum2, series, p_min, harm, hw, useries;
     size_t med[8];             // dtr x, y, z, rho0, c0sq, nl, ta, tb
     size_t u[3], rho[3], rho_total;
     size_t S[7];
@@ -246,6 +246,8 @@ struct Counts {
     int n_elem = 0, n_samples = 0;
     uint32_t record = 0;
     int capacity = 0;
+    int n_harm = 0;
+    double harm_freq = 0.0;
 };
 
 Layout make_layout(const kw_grid *g, const kw_medium *m, const Counts &c) {
@@ -295,6 +297,13 @@ Layout make_layout(const kw_grid *g, const kw_medium *m, const Counts &c) {
         L.p_sum2 = cv.take(nrec * sizeof(float));
     if (!c.sen_all && c.n_sen > 0 && (c.record & KW_REC_P_SERIES) && c.capacity > 0)
         L.series = cv.take((size_t)c.capacity * c.n_sen * sizeof(float));
+    if (nrec > 0 && (c.record & KW_REC_P_MIN)) L.p_min = cv.take(nrec * sizeof(float));
+    if (nrec > 0 && (c.record & KW_REC_HARMONICS)) {
+        L.harm = cv.take((size_t)2 * c.n_harm * nrec * sizeof(float));
+        L.hw = cv.take((size_t)2 * c.n_harm * sizeof(float));
+    }
+    if (!c.sen_all && c.n_sen > 0 && (c.record & KW_REC_U_SERIES) && c.capacity > 0)
+        L.useries = cv.take((size_t)c.capacity * 3 * c.n_sen * sizeof(float));
     const MediumShape ms = medium_shape(m);
     for (int i = 0; i < 8; ++i)
         if (ms.het[i]) L.med[i] = cv.take(N * sizeof(float));
@@ -365,7 +374,7 @@ int validate(const kw_grid *g, const kw_medium *m, const kw_source *s, const kw_
         return fail(KW_EINVAL, "source n_points must be >= 0");
     }
     if (z) {
-        if (z->record & ~63u) return fail(KW_EINVAL, "unknown record bits");
+        if (z->record & ~511u) return fail(KW_EINVAL, "unknown record bits");
         if (z->record_start < 1) return fail(KW_EINVAL, "record_start must be >= 1");
         c.record = z->record;
         c.capacity = z->series_capacity;
@@ -385,6 +394,21 @@ int validate(const kw_grid *g, const kw_medium *m, const kw_source *s, const kw_
         }
         if ((z->record & KW_REC_P_SERIES) && z->series_capacity < 1)
             return fail(KW_EINVAL, "a pressure series needs series_capacity >= 1");
+        if (z->record & KW_REC_U_SERIES) {
+            if (!z->index) return fail(KW_EINVAL, "a velocity series needs a sensor index list");
+            if (z->series_capacity < 1)
+                return fail(KW_EINVAL, "a velocity series needs series_capacity >= 1");
+        }
+        if (z->record & KW_REC_HARMONICS) {
+            if (z->n_harmonics < 1 || z->n_harmonics > 16)
+                return fail(KW_EINVAL, "n_harmonics = %d outside [1, 16]", z->n_harmonics);
+            const double f = z->harmonic_freq > 0.0 ? z->harmonic_freq
+                                                    : (s && s->n_points > 0 ? s->freq : 0.0);
+            if (!(f > 0.0) || !std::isfinite(f))
+                return fail(KW_EINVAL, "harmonics need harmonic_freq > 0 or a source frequency");
+            c.n_harm = z->n_harmonics;
+            c.harm_freq = f;
+        }
     }
     return KW_OK;
 }
@@ -524,7 +548,10 @@ hipError_t enqueue_step(kw_sim *s) {
         m.het[MED_TA] = s->med.ta.map != nullptr;
         return m;
     }();
-    const double sens_units = (s->sen.all_points ? ((s->sen.p_max ? 2 : 0) + (s->sen.p_sum2 ? 2 : 0)) : 0);
+    const double sens_units = (s->sen.all_points ? ((s->sen.p_max ? 2 : 0) + (s->sen.p_sum2 ? 2 : 0) +
+                                                    (s->sen.p_min ? 2 : 0) +
+                                                    (s->sen.harm ? 4 * s->sen.n_harm : 0))
+                                                 : 0);
     hipError_t e;
     int nk = 0;
 #define KW_L(cls, units, call)                                                  \
@@ -537,11 +564,11 @@ hipError_t enqueue_step(kw_sim *s) {
     float2 *s0[1] = {S[0]};
     float2 *s123[3] = {S[1], S[2], S[3]};
     float2 *s456[3] = {S[4], S[5], S[6]};
-    KW_L(KC_YFWD, 2, launch_ypass(st, g, c, t, s0, 1, false, &s->counters, &s->src));
+    KW_L(KC_YFWD, 2, launch_ypass(st, g, c, t, s0, 1, false, &s->counters, &s->src, &s->sen));
     KW_L(KC_ZGRAD, 4, launch_zfused(st, g, c, t, ZM_GRAD, s0, s123));
     KW_L(KC_YINV, 6, launch_ypass(st, g, c, t, s123, 3, true, nullptr, nullptr));
     KW_L(KC_XVEL, 12 + (ms.het[MED_DTRX] ? 3 : 0),
-         launch_xvel(st, g, c, t, s->med, s123, s->buf.u));
+         launch_xvel(st, g, c, t, s->med, s123, s->buf.u, s->sen, s->counters));
     KW_L(KC_YFWD, 6, launch_ypass(st, g, c, t, s123, 3, false, nullptr, nullptr));
     KW_L(KC_ZDIV, 6, launch_zfused(st, g, c, t, ZM_DIV, s123, s456));
     KW_L(KC_YINV, 6, launch_ypass(st, g, c, t, s456, 3, true, nullptr, nullptr));
@@ -956,6 +983,14 @@ int kw_create(const kw_grid *grid, const kw_medium *medium, const kw_source *sou
     if (L.p_max) se.p_max = s->at<float>(L.p_max);
     if (L.p_sum2) se.p_sum2 = s->at<float>(L.p_sum2);
     if (L.series) se.series = s->at<float>(L.series);
+    if (L.p_min) se.p_min = s->at<float>(L.p_min);
+    if (L.harm) {
+        se.harm = s->at<float>(L.harm);
+        se.hw = s->at<float>(L.hw);
+        se.n_harm = cnt.n_harm;
+        se.harm_wdt = 2.0 * kPi * cnt.harm_freq * dt;
+    }
+    if (L.useries) se.u_series = s->at<float>(L.useries);
 
     // tables
     Tables &t = s->tab;
@@ -1028,6 +1063,10 @@ int kw_create(const kw_grid *grid, const kw_medium *medium, const kw_source *sou
     z(se.p_max, nrec, -INFINITY);
     z(se.p_sum2, nrec, 0.0f);
     z(se.series, (size_t)cnt.capacity * cnt.n_sen, 0.0f);
+    z(se.p_min, nrec, INFINITY);
+    z(se.harm, (size_t)2 * cnt.n_harm * nrec, 0.0f);
+    z(se.hw, (size_t)2 * cnt.n_harm, 0.0f);
+    z(se.u_series, (size_t)cnt.capacity * 3 * cnt.n_sen, 0.0f);
     z(sd.drive, std::max(1, cnt.n_elem), 0.0f);
     if (e == hipSuccess) e = launch_fill_int(s->stream, s->counters.step, 1, 0);
     if (e == hipSuccess) e = launch_fill_int(s->stream, s->counters.nonfinite, 1, INT_MAX);
@@ -1068,9 +1107,16 @@ int64_t kw_gather_bytes(kw_sim *s, uint32_t what) {
     const size_t nrec = s->cnt.sen_all ? N : (size_t)s->cnt.n_sen;
     switch (what) {
     case KW_REC_P_MAX:
+    case KW_REC_P_MIN:
     case KW_REC_P_RMS:
     case KW_REC_INTENSITY:
         return (int64_t)(nrec * sizeof(float));
+    case KW_REC_HARMONICS:
+        return (int64_t)((size_t)2 * s->cnt.n_harm * nrec * sizeof(float));
+    case KW_REC_U_SERIES: {
+        const long rec = std::max(0L, s->steps - s->record_start + 1);
+        return (int64_t)(std::min<long>(rec, s->cnt.capacity) * 3 * s->cnt.n_sen * sizeof(float));
+    }
     case KW_REC_P_SERIES: {
         const long rec = std::max(0L, s->steps - s->record_start + 1);
         return (int64_t)(std::min<long>(rec, s->cnt.capacity) * s->cnt.n_sen * sizeof(float));
@@ -1107,6 +1153,30 @@ int kw_gather(kw_sim *s, uint32_t what, void *dst, size_t dst_bytes, int dst_is_
     case KW_REC_P_MAX:
         rc = copy_out(s, dst, s->sen.p_max, need, dst_is_device);
         break;
+    case KW_REC_P_MIN:
+        rc = copy_out(s, dst, s->sen.p_min, need, dst_is_device);
+        break;
+    case KW_REC_U_SERIES:
+        if (need > 0) rc = copy_out(s, dst, s->sen.u_series, need, dst_is_device);
+        break;
+    case KW_REC_HARMONICS: {
+        // A_h = (2 / N) times the accumulated sums
+        const float scale = nrec_steps > 0 ? (float)(2.0 / nrec_steps) : 0.0f;
+        const size_t n = (size_t)need / sizeof(float);
+        if (dst_is_device) {
+            hipError_t e = launch_scale(s->stream, s->sen.harm, reinterpret_cast<float *>(dst), n,
+                                        scale);
+            if (e != hipSuccess) return fail(KW_EDEVICE, "scale: %s", hipGetErrorString(e));
+        } else {
+            rc = copy_out(s, dst, s->sen.harm, need, 0);
+            if (rc == KW_OK) {
+                KW_HIP(hipStreamSynchronize(s->stream));
+                float *h = reinterpret_cast<float *>(dst);
+                for (size_t i = 0; i < n; ++i) h[i] *= scale;
+            }
+        }
+        break;
+    }
     case KW_REC_P_RMS:
     case KW_REC_INTENSITY: {
         float *target = dst_is_device ? reinterpret_cast<float *>(dst) : tmp;
@@ -1290,6 +1360,11 @@ std::vector<std::pair<void *, size_t>> state_regions(kw_sim *s) {
     if (s->sen.p_sum2) r.emplace_back(s->sen.p_sum2, nrec * sizeof(float));
     if (s->sen.series)
         r.emplace_back(s->sen.series, (size_t)s->cnt.capacity * s->cnt.n_sen * sizeof(float));
+    if (s->sen.p_min) r.emplace_back(s->sen.p_min, nrec * sizeof(float));
+    if (s->sen.harm)
+        r.emplace_back(s->sen.harm, (size_t)2 * s->cnt.n_harm * nrec * sizeof(float));
+    if (s->sen.u_series)
+        r.emplace_back(s->sen.u_series, (size_t)s->cnt.capacity * 3 * s->cnt.n_sen * sizeof(float));
     return r;
 }
 

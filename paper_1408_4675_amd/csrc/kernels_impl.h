@@ -140,6 +140,11 @@ struct YArgs {
     int prologue;
     Counters cnt;
     SourceDev src;
+    // and cos, sin of h w t (h = 1..n_harm) at t = (n + 1) dt, the time of
+    // the pressure this step produces, for the harmonic sums of the sensors
+    float *hw;
+    int n_harm;
+    double harm_wdt;
 };
 
 // MAXT: 512, or 1024 for the wide column tiles of long axes (fixed engines
@@ -162,6 +167,11 @@ __global__ void __launch_bounds__(MAXT) kw_ypass(YArgs a) {
         __syncthreads();
         if (tid == 0) *a.cnt.step = n + 1;
         for (int e = tid; e < a.src.n_elements; e += blockDim.x) a.src.drive[e] = drive_at(a.src, e, n);
+        for (int h = tid; h < a.n_harm; h += blockDim.x) {
+            const double th = a.harm_wdt * (double)(h + 1) * (double)(n + 1);
+            a.hw[2 * h] = (float)cos(th);
+            a.hw[2 * h + 1] = (float)sin(th);
+        }
     }
 
     float2 v[E];
@@ -515,7 +525,8 @@ __device__ __forceinline__ void row_r2c(const XArgs &a, float2 *__restrict__ row
     (void)nx; (void)rbase; (void)cupd;
 
 // The three velocity components are independent: blockIdx.y selects one.
-template <class Eng>
+// USER: record u at the mask sensor points (the variant with the row scan).
+template <class Eng, bool USER>
 __global__ void __launch_bounds__(512) kw_xvel(XArgs a) {
     KW_XPROLOGUE
     const int iy = rr % a.g.ny, iz = rr / a.g.ny;
@@ -543,6 +554,36 @@ __global__ void __launch_bounds__(512) kw_xvel(XArgs a) {
                 un.y = q.y * (q.y * u0.y - d.y * g.y);
                 st2(u, i, un);
                 v[m] = un;
+            }
+        }
+    }
+    if constexpr (USER) {
+        // u^(n+1/2) is recorded with p^(n+1): step counter n + 1, already advanced
+        const int step = *a.cnt.step;
+        const int slot = step - a.sen.record_start;
+        if (step >= a.sen.record_start && slot < a.sen.capacity) {
+            int beg = 0, end = 0;
+            if (ok) {
+                beg = a.sen.row_ptr[rr];
+                end = a.sen.row_ptr[rr + 1];
+            }
+            if (__syncthreads_or(end > beg)) {
+                float *mine = reinterpret_cast<float *>(sh + (size_t)a.tb * row_pitch(M)) + (size_t)b * nx;
+                if (ok) {
+#pragma unroll
+                    for (int m = 0; m < E; ++m) {
+                        if (m < cupd) {
+                            const int x = 2 * Eng::out_index(a.pi, t, m);
+                            mine[x] = v[m].x;
+                            mine[x + 1] = v[m].y;
+                        }
+                    }
+                }
+                __syncthreads();
+                for (int e = beg + t; e < end; e += L)
+                    a.sen.u_series[((size_t)slot * 3 + xi) * a.sen.n_points + a.sen.sid[e]] =
+                        mine[a.sen.xpos[e]];
+                __syncthreads();
             }
         }
     }
@@ -605,16 +646,25 @@ __device__ __forceinline__ void record_mask(const XArgs &a, float *line, int row
         const int id = a.sen.sid[e];
         const float pv = mine[a.sen.xpos[e]];
         if (a.sen.p_max) a.sen.p_max[id] = fmaxf(a.sen.p_max[id], pv);
+        if (a.sen.p_min) a.sen.p_min[id] = fminf(a.sen.p_min[id], pv);
         if (a.sen.p_sum2) a.sen.p_sum2[id] += pv * pv;
         if (a.sen.series && slot < a.sen.capacity)
             a.sen.series[(size_t)slot * a.sen.n_points + id] = pv;
+        for (int h = 0; h < a.sen.n_harm; ++h) {
+            // p e^{-i h w t}
+            float2 *acc = reinterpret_cast<float2 *>(a.sen.harm) + (size_t)h * a.sen.n_points + id;
+            const float c = a.sen.hw[2 * h], sn = a.sen.hw[2 * h + 1];
+            *acc = make_float2(acc->x + pv * c, acc->y - pv * sn);
+        }
     }
     __syncthreads();
 }
 
 // sensors, non-finite check and x r2c of the new pressure (v holds p in the
 // output layout of the inverse x transform)
-template <class Eng, bool MASK = true>
+// SENS: the rarer sensor work is compiled in (mask sensors, p_min, harmonic
+// sums); without it the register count of the common case stays lower
+template <class Eng, bool SENS = true>
 __device__ __forceinline__ void finish_pressure(const XArgs &a, float *line, int row, bool ok,
                                                 int t, int L, int b, const RowLds &lds,
                                                 float2 (&v)[Eng::E], const float2 *twx,
@@ -642,12 +692,27 @@ __device__ __forceinline__ void finish_pressure(const XArgs &a, float *line, int
                         const float2 s = ld2(a.sen.p_sum2, i);
                         st2(a.sen.p_sum2, i, make_float2(s.x + p.x * p.x, s.y + p.y * p.y));
                     }
+                    if constexpr (SENS) {
+                        if (a.sen.p_min) {
+                            const float2 mn = ld2(a.sen.p_min, i);
+                            st2(a.sen.p_min, i, make_float2(fminf(mn.x, p.x), fminf(mn.y, p.y)));
+                        }
+                        const size_t nrec = (size_t)a.g.nx * a.g.rows;
+                        for (int h = 0; h < a.sen.n_harm; ++h) {
+                            // points i, i+1: (re, im) pairs of p e^{-i h w t}
+                            float4 *acc = reinterpret_cast<float4 *>(a.sen.harm + 2 * ((size_t)h * nrec + i));
+                            const float c = a.sen.hw[2 * h], sn = a.sen.hw[2 * h + 1];
+                            const float4 o = *acc;
+                            *acc = make_float4(o.x + p.x * c, o.y - p.x * sn, o.z + p.y * c,
+                                               o.w - p.y * sn);
+                        }
+                    }
                 }
             }
         }
     }
     if (bad) atomicMin(a.cnt.nonfinite, step);
-    if constexpr (MASK) {
+    if constexpr (SENS) {
         if (rec && !a.sen.all_points && a.sen.row_ptr)
             record_mask<Eng>(a, line, row, ok, t, L, b, step, v);
     }
@@ -797,11 +862,10 @@ __global__ void __launch_bounds__(512) kw_xden(XArgs a) {
     }
 }
 
-// MASK: mask sensors are recorded (their row scan is compiled in only then,
-// which keeps the register count of the all-points and no-sensor cases lower)
+// SENS: mask sensors, p_min or harmonic sums are recorded (see finish_pressure)
 // Asked to fit six wavefronts per SIMD (80 registers; a few bytes spill):
 // measured faster than five without spills.
-template <class Eng, bool MASK>
+template <class Eng, bool SENS>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6))) kw_xeos(XArgs a) {
     KW_XPROLOGUE
     float *line = reinterpret_cast<float *>(sh + (size_t)a.tb * row_pitch(M));
@@ -829,7 +893,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6))) k
             }
         }
     }
-    finish_pressure<Eng, MASK>(a, line, rr, ok, t, L, b, lds, v, tws, tws + M);
+    finish_pressure<Eng, SENS>(a, line, rr, ok, t, L, b, lds, v, tws, tws + M);
 }
 
 template <class Eng>

@@ -8,6 +8,12 @@ __global__ void kw_fill(float *p, size_t n, float v) {
          i += (size_t)gridDim.x * blockDim.x)
         p[i] = v;
 }
+__global__ void kw_scale(const float *src, float *dst, size_t n, float scale) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = src[i] * scale;
+}
+
 __global__ void kw_fill_int(int *p, size_t n, int v) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (size_t)gridDim.x * blockDim.x)
@@ -37,6 +43,10 @@ static inline dim3 flat_grid(size_t n) {
 
 hipError_t launch_fill(hipStream_t s, float *p, size_t n, float v) {
     hipLaunchKernelGGL(kw_fill, flat_grid(n), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+hipError_t launch_scale(hipStream_t s, const float *src, float *dst, size_t n, float scale) {
+    hipLaunchKernelGGL(kw_scale, flat_grid(n), dim3(256), 0, s, src, dst, n, scale);
     return hipGetLastError();
 }
 hipError_t launch_fill_int(hipStream_t s, int *p, size_t n, int v) {

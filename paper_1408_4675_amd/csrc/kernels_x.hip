@@ -25,15 +25,27 @@ static inline size_t x_lds(const GridDev &g, const LaunchCfg &c, bool line) {
     } while (0)
 
 hipError_t launch_xvel(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
-                       const Medium &m, float2 *const *S, float *const *u) {
+                       const Medium &m, float2 *const *S, float *const *u,
+                       const SensorDev &sen, const Counters &cnt) {
     XArgs a = make_xargs(g, c, t);
     a.m = m;
+    a.sen = sen;
+    a.cnt = cnt;
     for (int i = 0; i < 3; ++i) {
         a.Sin[i] = S[i];
         a.Sout[i] = S[i];
         a.fld[i] = u[i];
     }
-    KW_XLAUNCH_N(kw_xvel, false, 3);
+    dim3 grid((g.rows + c.tb_x - 1) / c.tb_x, 3);
+    dim3 block(c.tb_x * c.px.L);
+    if (sen.u_series) {
+        // velocity series at mask sensor points: the variant with the row scan
+        const size_t lds = x_lds(g, c, true);
+        KW_ENGINE_SWITCH(c.eng_x, hipLaunchKernelGGL((kw_xvel<Eng, true>), grid, block, lds, s, a));
+    } else {
+        const size_t lds = x_lds(g, c, false);
+        KW_ENGINE_SWITCH(c.eng_x, hipLaunchKernelGGL((kw_xvel<Eng, false>), grid, block, lds, s, a));
+    }
     return hipGetLastError();
 }
 
@@ -78,10 +90,11 @@ hipError_t launch_xeos(hipStream_t s, const GridDev &g, const LaunchCfg &c, cons
     a.Sout[0] = Sout;
     // the per-row line is only needed to pick mask sensor points out of a row
     const bool mask = sen.row_ptr != nullptr && !sen.all_points;
+    const bool extra = sen.p_min != nullptr || sen.harm != nullptr;
     dim3 grid((g.rows + c.tb_x - 1) / c.tb_x);
     dim3 block(c.tb_x * c.px.L);
     const size_t lds = x_lds(g, c, mask);
-    if (mask) {
+    if (mask || extra) {
         KW_ENGINE_SWITCH(c.eng_x, hipLaunchKernelGGL((kw_xeos<Eng, true>), grid, block, lds, s, a));
     } else {
         KW_ENGINE_SWITCH(c.eng_x, hipLaunchKernelGGL((kw_xeos<Eng, false>), grid, block, lds, s, a));

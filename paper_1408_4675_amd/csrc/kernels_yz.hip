@@ -5,7 +5,7 @@ namespace kw {
 
 hipError_t launch_ypass(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
                         float2 *const *fields, int nfields, bool inverse,
-                        const Counters *prologue, const SourceDev *src) {
+                        const Counters *prologue, const SourceDev *src, const SensorDev *sen) {
     YArgs a{};
     for (int i = 0; i < nfields; ++i) a.f[i] = fields[i];
     a.M = g.M;
@@ -16,6 +16,11 @@ hipError_t launch_ypass(hipStream_t s, const GridDev &g, const LaunchCfg &c, con
     a.prologue = prologue != nullptr;
     if (prologue) a.cnt = *prologue;
     if (src) a.src = *src;
+    if (sen && sen->harm) {
+        a.hw = sen->hw;
+        a.n_harm = sen->n_harm;
+        a.harm_wdt = sen->harm_wdt;
+    }
     dim3 grid((g.M + a.tb - 1) / a.tb, g.nz, nfields);
     dim3 block(a.tb * a.plan.L);
     size_t lds = col_lds_bytes(g.ny, a.tb);

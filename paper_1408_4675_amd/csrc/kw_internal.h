@@ -90,6 +90,12 @@ struct SensorDev {
     float *series;           // [capacity * n_points] or null
     int capacity;
     int record_start;
+    float *p_min;            // null when not recorded
+    float *harm;             // [n_harm][points][2] running sums of p e^{-i h w t}, or null
+    float *hw;               // [n_harm][2] cos, sin of h w t for the step being recorded
+    int n_harm;
+    double harm_wdt;         // 2 pi f dt of the harmonic base frequency
+    float *u_series;         // [capacity][3][n_points] or null
 };
 
 struct Medium {
@@ -193,11 +199,13 @@ struct AdjDev {
 // launchers (kernels_yz.hip, kernels_x.hip, kernels_util.hip, kernels_adj.hip) ------
 hipError_t launch_ypass(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
                         float2 *const *fields, int nfields, bool inverse,
-                        const Counters *prologue, const SourceDev *src);
+                        const Counters *prologue, const SourceDev *src,
+                        const SensorDev *sen = nullptr);
 hipError_t launch_zfused(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
                          int mode, float2 *const *in, float2 *const *out);
 hipError_t launch_xvel(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
-                       const Medium &m, float2 *const *S, float *const *u);
+                       const Medium &m, float2 *const *S, float *const *u,
+                       const SensorDev &sen, const Counters &cnt);
 hipError_t launch_xden(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
                        const Medium &m, const SourceDev &src, const SensorDev &sen,
                        const Counters &cnt, float2 *const *Sin, float *const *rho,
@@ -226,6 +234,7 @@ hipError_t launch_adj_sum(hipStream_t s, const GridDev &g, const AdjDev &a);
 hipError_t launch_adj_objective(hipStream_t s, const GridDev &g, const float *w,
                                 const float *sum2, double *out);
 hipError_t launch_fill(hipStream_t s, float *p, size_t n, float v);
+hipError_t launch_scale(hipStream_t s, const float *src, float *dst, size_t n, float scale);
 hipError_t launch_fill_int(hipStream_t s, int *p, size_t n, int v);
 // dst[i] = f(sum2[i]) for the gather of p_rms / intensity
 hipError_t launch_finalize(hipStream_t s, const float *sum2, float *dst, size_t n, float inv_count,

@@ -35,6 +35,9 @@ REC_P_SERIES = 4
 REC_P_FINAL = 8
 REC_U_FINAL = 16
 REC_INTENSITY = 32
+REC_P_MIN = 64
+REC_HARMONICS = 128
+REC_U_SERIES = 256
 
 # water, the coupling medium of the paper's application (Section 5)
 WATER = dict(c0=1500.0, rho0=1000.0, alpha0=0.75, bona=5.0)
@@ -95,6 +98,8 @@ class Sensor:
     index: Optional[np.ndarray] = None     # None -> every grid point
     record_start: int = 1                  # first step number whose pressure is recorded
     series_capacity: int = 0
+    n_harmonics: int = 0                   # harmonics 1..n of harmonic_freq (REC_HARMONICS)
+    harmonic_freq: float = 0.0             # 0 -> the source frequency
 
 
 @dataclass

@@ -73,9 +73,11 @@ class _Marshalled:
             sidx = np.ascontiguousarray(z.index, np.int64)
             self.keep.append(sidx)
             self.sensor = A.KwSensor(z.record, sidx.size, sidx.ctypes.data_as(_P(C.c_int64)),
-                                     z.record_start, z.series_capacity)
+                                     z.record_start, z.series_capacity, z.n_harmonics,
+                                     z.harmonic_freq)
         else:
-            self.sensor = A.KwSensor(z.record, 0, None, z.record_start, z.series_capacity)
+            self.sensor = A.KwSensor(z.record, 0, None, z.record_start, z.series_capacity,
+                                     z.n_harmonics, z.harmonic_freq)
 
     def args(self):
         return (C.byref(self.grid), C.byref(self.medium), C.byref(self.source),

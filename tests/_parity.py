@@ -39,6 +39,17 @@ def compare_outputs(sim, orc, scen, report, tol=None):
         errs["p_series"] = rel_l2(ser, ref)
     if rec & sc.REC_INTENSITY:
         errs["intensity"] = rel_l2(sim.gather(A.KW_REC_INTENSITY, device=False), orc.intensity())
+    if rec & sc.REC_P_MIN:
+        errs["p_min"] = rel_l2(sim.gather(A.KW_REC_P_MIN, device=False), orc.p_min)
+    if rec & sc.REC_HARMONICS:
+        h = sim.gather(A.KW_REC_HARMONICS, device=False).reshape(scen.sensor.n_harmonics, -1, 2)
+        ref = orc.harmonics()
+        errs["harmonics"] = rel_l2(np.stack([h[..., 0], h[..., 1]]),
+                                   np.stack([ref.real, ref.imag]))
+    if rec & sc.REC_U_SERIES:
+        u = sim.gather(A.KW_REC_U_SERIES, device=False)
+        ref = orc.u_series_array()[: scen.sensor.series_capacity]
+        errs["u_series"] = rel_l2(u, ref)
     report.append((scen.name, errs, tol))
     print("parity %-28s tol %.0e  %s" % (scen.name, tol,
           "  ".join("%s %.2e" % kv for kv in errs.items())), flush=True)

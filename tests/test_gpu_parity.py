@@ -370,3 +370,32 @@ def test_snapshot_rejects_other_setup(kw):
     bad[:8] = 0
     with pytest.raises(A.KwError):
         s3.load(bad)
+
+
+# ---------------------------------------------------------------------------
+# on-device reductions: peak negative pressure, harmonic amplitudes, velocity
+# series at mask points
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mask", [True, False])
+def test_parity_pmin_harmonics_useries(kw, mask):
+    A, Simulation = kw
+    steps = 40
+    scen = sc.small_case(48, 20, 18, seed=17, steps=steps, sensor_mask=mask, amp=2e6)
+    rec = sc.REC_P_MIN | sc.REC_HARMONICS | sc.REC_P_MAX
+    if mask:
+        rec |= sc.REC_U_SERIES | sc.REC_P_SERIES
+    scen = scen.replace(sensor=sc.Sensor(record=rec, index=scen.sensor.index if mask else None,
+                                         record_start=9, series_capacity=steps, n_harmonics=3))
+    scen = scen.replace(name=scen.name + ("_mask" if mask else "_all"))
+    sim, orc = _run_both(kw, scen, steps)
+    errs, tol = compare_outputs(sim, orc, scen, REPORT)
+    assert set(errs) >= {"p_min", "harmonics"}
+    for k, e in errs.items():
+        assert e <= tol, (k, e)
+    # a snapshot round trip keeps the new accumulators too
+    snap = sim.save(device=True)
+    sim2 = Simulation(scen)
+    sim2.load(snap)
+    for what in (A.KW_REC_P_MIN, A.KW_REC_HARMONICS):
+        assert np.array_equal(sim.gather(what, device=False), sim2.gather(what, device=False))

@@ -475,3 +475,83 @@ def test_fft_count_per_step():
     o = Oracle(_case(6, 6, 6, nonlinear=False, absorbing=False))
     o.step(2)
     assert o.fft_forward + o.fft_inverse == 20              # 10 per step
+
+
+# ---------------------------------------------------------------------------
+# on-the-fly reductions of the recorded pressure: peak negative pressure and
+# harmonic amplitudes, pinned by the exact plane wave
+# ---------------------------------------------------------------------------
+
+def test_harmonics_and_peak_negative_of_exact_plane_wave():
+    """Lossless periodic medium, on-grid oblique wave p = A cos(k.x - w t) (the
+    scheme is exact for it).  Over a window of whole periods the first harmonic
+    amplitude of p at every point is A e^{-i k.x} (p = A cos(w t - k.x)), the others vanish, and the
+    running minimum is -A to within the sampling of one period."""
+    from oracle import Oracle
+    from paper_1408_4675_amd import scenarios as sc
+    n = 16
+    dx = 1e-4
+    c0 = 1500.0
+    kvec = 2 * np.pi * np.array([2, 1, 1]) / (n * dx)
+    k = np.linalg.norm(kvec)
+    w = c0 * k
+    period = 2 * np.pi / w
+    per_period = 40
+    dt = period / per_period
+    g = sc.Grid(n, n, n, dx, dx, dx, dt=dt, cfl=0.0, pml_size=(0, 0, 0))
+    med = sc.Medium(c0, 1000.0, 0.0, 5.0, 1.5, nonlinear=False, absorbing=False)
+    steps = 3 * per_period
+    sen = sc.Sensor(record=sc.REC_P_MIN | sc.REC_HARMONICS, record_start=steps - 2 * per_period + 1,
+                    n_harmonics=3, harmonic_freq=w / (2 * np.pi))
+    scen = sc.Scenario("plane", g, med, None, sen, steps)
+    o = Oracle(scen)
+    z, y, x = np.meshgrid(np.arange(n) * dx, np.arange(n) * dx, np.arange(n) * dx, indexing="ij")
+    A = 1e5
+    phase = kvec[0] * x + kvec[1] * y + kvec[2] * z
+    p0 = A * np.cos(phase)
+    o.set_pressure(p0)
+    # staggered velocity at t = -dt/2 of the travelling wave
+    for a in range(3):
+        shifted = phase + kvec[a] * dx / 2
+        o.u[a] = A * kvec[a] / (1000.0 * c0 * k) * np.cos(shifted + w * dt / 2)
+    o.step(steps)
+    H = o.harmonics()
+    expect = (A * np.exp(-1j * phase)).reshape(-1)
+    assert np.max(np.abs(H[0] - expect)) < 1e-8 * A
+    assert np.max(np.abs(H[1])) < 1e-8 * A and np.max(np.abs(H[2])) < 1e-8 * A
+    # minimum over 80 samples of a cosine: within A (1 - cos(pi / 40))
+    assert np.all(o.p_min <= -A * np.cos(np.pi / per_period) * (1 - 1e-9))
+    assert np.all(o.p_min >= -A * (1 + 1e-9))
+
+
+def test_velocity_series_of_exact_plane_wave():
+    """u^(m-1/2) recorded with p^m at mask points equals the travelling wave
+    at its staggered position and half-step time."""
+    from oracle import Oracle
+    from paper_1408_4675_amd import scenarios as sc
+    n, dx, c0, rho0 = 16, 1e-4, 1500.0, 1000.0
+    kvec = 2 * np.pi * np.array([1, 2, 1]) / (n * dx)
+    k = np.linalg.norm(kvec)
+    w = c0 * k
+    dt = 0.3 * dx / c0
+    g = sc.Grid(n, n, n, dx, dx, dx, dt=dt, cfl=0.0, pml_size=(0, 0, 0))
+    med = sc.Medium(c0, rho0, 0.0, 5.0, 1.5, nonlinear=False, absorbing=False)
+    idx = np.array([5, 700, 1801, 4000], np.int64)
+    steps = 12
+    sen = sc.Sensor(record=sc.REC_P_SERIES | sc.REC_U_SERIES, index=idx, record_start=3,
+                    series_capacity=steps)
+    o = Oracle(sc.Scenario("plane_u", g, med, None, sen, steps))
+    z, y, x = np.meshgrid(np.arange(n) * dx, np.arange(n) * dx, np.arange(n) * dx, indexing="ij")
+    A = 1e5
+    phase = kvec[0] * x + kvec[1] * y + kvec[2] * z
+    o.set_pressure(A * np.cos(phase))
+    for a in range(3):
+        o.u[a] = A * kvec[a] / (rho0 * c0 * k) * np.cos(phase + kvec[a] * dx / 2 + w * dt / 2)
+    o.step(steps)
+    us = o.u_series_array()
+    assert us.shape == (steps - 2, 3, idx.size)
+    for r in range(us.shape[0]):
+        m = r + 3
+        for a in range(3):
+            ex = A * kvec[a] / (rho0 * c0 * k) * np.cos(phase + kvec[a] * dx / 2 - w * (m - 0.5) * dt)
+            assert np.max(np.abs(us[r, a] - ex.reshape(-1)[idx])) < 1e-9 * A / (rho0 * c0)
