@@ -101,21 +101,38 @@ typedef struct kw_medium {
     uint32_t flags;                               /* KW_NONLINEAR | KW_ABSORBING  */
 } kw_medium;
 
-/* Pressure drive s_e(t) [Pa] of each element, injected at the listed grid
- * points as an additive mass source split evenly over the three density
- * components (M_xi = 2 s / (3 c0 dx)) at t = (n + 1/2) dt, Eq. (4d).
- * s_e = amp[e] sin(2 pi freq t + phase[e]), or signal[e * n_samples + n]
- * when signal is non-NULL (0 after the last sample). */
+/* Source kinds (the source enters the model through the mass source term of
+ * Eq. (4d) or the force term of Eq. (4b); Section 3.4 describes injection as
+ * updating the pressure or the particle velocity at the source points):
+ *   KW_SOURCE_MASS      s_e [Pa] as an additive mass source split evenly over
+ *                       the three density components, M_xi = 2 s / (3 c0 dx),
+ *                       added after the update of Eq. (4d), at t = (n + 1/2) dt;
+ *   KW_SOURCE_FORCE     s_e [m/s^2] as an additive force per unit mass F on
+ *                       the velocity component `axis`, u += dt F after the
+ *                       update of Eq. (4b), at t = n dt;
+ *   KW_SOURCE_PRESSURE  Dirichlet: p^(n+1) = s_e [Pa] at the points after the
+ *                       equation of state, at t = (n + 1) dt (the densities
+ *                       are not changed). */
+#define KW_SOURCE_MASS      0
+#define KW_SOURCE_FORCE     1
+#define KW_SOURCE_PRESSURE  2
+
+/* Drive s_e(t) of each element at the listed grid points:
+ * s_e = amp[e] sin(2 pi freq t + phase[e]) with t as stated for the kind, or
+ * signal[e * n_samples + n] in step n when signal is non-NULL (0 after the
+ * last sample). */
 typedef struct kw_source {
     int64_t        n_points;     /* 0 -> no source                                 */
     const int64_t *index;        /* flat indices, strictly increasing               */
     const int32_t *element;      /* element of each point; NULL -> all element 0   */
     int32_t        n_elements;   /* >= 1 when n_points > 0                          */
-    const float   *amp;          /* [n_elements] Pa                                 */
+    const float   *amp;          /* [n_elements] (unit of the kind)                 */
     const float   *phase;        /* [n_elements] rad                                */
     double         freq;         /* Hz                                              */
     const float   *signal;       /* optional [n_elements * n_samples]               */
     int32_t        n_samples;
+    int32_t        kind;         /* KW_SOURCE_*                                     */
+    int32_t        axis;         /* KW_SOURCE_FORCE: 0 = x, 1 = y, 2 = z            */
 } kw_source;
 
 /* Sensor: quantities in `record` are kept for the points in `index` (strictly

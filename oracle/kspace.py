@@ -28,6 +28,10 @@ is also listed in the design notes):
     over the three density components, M_xi = 2 s / (3 c0 dx), added after the
     division of Eq. (4d), sampled at t = (n + 1/2) dt:
         s_e(n+1/2) = a_e sin(2 pi f (n + 1/2) dt + phi_e).
+  * Other source kinds: a force per unit mass F on one velocity component
+    (the F term of Eq. (4b)), u += dt F after the update, sampled at t = n dt;
+    a pressure source imposes p^(n+1) = s at its points after the equation of
+    state, sampled at t = (n + 1) dt, leaving the densities as they are.
   * k^(y-2) and k^(y-1) are set to 0 at k = 0.
   * Absorption coefficient: alpha0 [Np (rad/s)^-y m^-1]
         = 100 alpha0[dB/(MHz^y cm)] / (20 log10 e) / (2 pi 1e6)^y.
@@ -176,7 +180,8 @@ class Oracle:
                             phase=np.asarray(src.phase, np.float64),
                             freq=float(src.freq),
                             signal=None if src.signal is None
-                            else np.asarray(src.signal, np.float64))
+                            else np.asarray(src.signal, np.float64),
+                            kind=int(getattr(src, "kind", 0)), axis=int(getattr(src, "axis", 0)))
 
         # optional tape for the discrete adjoint (oracle/adjoint.py): when a
         # list, every step appends the values its reverse pass needs
@@ -234,13 +239,14 @@ class Oracle:
         self.u = [np.asarray(v, np.float64).reshape(self.shape).copy() for v in (ux, uy, uz)]
 
     # -- the time step ---------------------------------------------------------
-    def source_values(self, n: int) -> np.ndarray:
-        """Drive value of each element at t = (n + 1/2) dt."""
+    def source_values(self, n: int, offset: float = 0.5) -> np.ndarray:
+        """Drive value of each element in step n, at t = (n + offset) dt (the
+        sampled signal gives sample n whatever the offset)."""
         s = self.src
         if s["signal"] is not None:
             sig = s["signal"]
             return sig[:, n] if n < sig.shape[1] else np.zeros(sig.shape[0])
-        t = (n + 0.5) * self.dt
+        t = (n + offset) * self.dt
         return s["amp"] * np.sin(2.0 * np.pi * s["freq"] * t + s["phase"])
 
     def pressure_gradient(self, p):
@@ -265,6 +271,11 @@ class Oracle:
         for a in range(3):
             q = self.pml_stag[a]
             self.u[a] = q * (q * self.u[a] - dt / self.rho0_stag[a] * grad[a])
+        # force source (the F term of Eq. (4b)), sampled at t = n dt
+        if self.src is not None and self.src["kind"] == 1:
+            s = self.src
+            flat = self.u[s["axis"]].reshape(-1)
+            np.add.at(flat, s["idx"], dt * self.source_values(self.n, 0.0)[s["elem"]])
         # (4c) velocity divergence, one component at a time
         div = self.velocity_divergence(self.u)
         # (4d) split density update (nonlinear denominator), PML, mass source
@@ -274,7 +285,7 @@ class Oracle:
             if self.nonlinear:
                 num = num / (1.0 + 2.0 * dt * div[a])
             self.rho[a] = num
-        if self.src is not None:
+        if self.src is not None and self.src["kind"] == 0:
             s = self.src
             add = dt * s["coef"] * self.source_values(self.n)[s["elem"]]
             for a in range(3):
@@ -296,6 +307,10 @@ class Oracle:
             self.p = self.c0 ** 2 * (rho + self.bona / (2.0 * self.rho0) * rho * rho - L_d)
         else:
             self.p = self.c0 ** 2 * (rho - L_d)
+        # pressure source: p^(n+1) imposed at the points, t = (n + 1) dt
+        if self.src is not None and self.src["kind"] == 2:
+            s = self.src
+            self.p.reshape(-1)[s["idx"]] = self.source_values(self.n, 1.0)[s["elem"]]
         self.n += 1
         if self.tape is not None:
             self.tape[-1]["p"] = self.p.copy()

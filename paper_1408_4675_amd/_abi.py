@@ -18,6 +18,10 @@ KW_ENONFINITE = -6
 STATUS_NAMES = {0: "KW_OK", -1: "KW_EINVAL", -2: "KW_EUNSUPPORTED", -3: "KW_ENOMEM",
                 -4: "KW_EDEVICE", -5: "KW_ESTATE", -6: "KW_ENONFINITE"}
 
+KW_SOURCE_MASS = 0
+KW_SOURCE_FORCE = 1
+KW_SOURCE_PRESSURE = 2
+
 KW_NONLINEAR = 1
 KW_ABSORBING = 2
 
@@ -67,7 +71,7 @@ class KwSource(C.Structure):
                 ("element", C.POINTER(C.c_int32)), ("n_elements", C.c_int32),
                 ("amp", C.POINTER(C.c_float)), ("phase", C.POINTER(C.c_float)),
                 ("freq", C.c_double), ("signal", C.POINTER(C.c_float)),
-                ("n_samples", C.c_int32)]
+                ("n_samples", C.c_int32), ("kind", C.c_int32), ("axis", C.c_int32)]
 
 
 class KwSensor(C.Structure):

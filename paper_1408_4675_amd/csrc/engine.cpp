@@ -359,6 +359,10 @@ int validate(const kw_grid *g, const kw_medium *m, const kw_source *s, const kw_
         if (!s->index || !s->amp || !s->phase) return fail(KW_EINVAL, "source arrays missing");
         if (s->n_elements < 1) return fail(KW_EINVAL, "source n_elements must be >= 1");
         if (s->signal && s->n_samples < 1) return fail(KW_EINVAL, "signal needs n_samples >= 1");
+        if (s->kind < KW_SOURCE_MASS || s->kind > KW_SOURCE_PRESSURE)
+            return fail(KW_EINVAL, "unknown source kind %d", s->kind);
+        if (s->kind == KW_SOURCE_FORCE && (s->axis < 0 || s->axis > 2))
+            return fail(KW_EINVAL, "force source axis %d outside [0, 2]", s->axis);
         for (long i = 0; i < s->n_points; ++i) {
             if (s->index[i] < 0 || s->index[i] >= N)
                 return fail(KW_EINVAL, "source index %ld out of the grid", (long)s->index[i]);
@@ -568,7 +572,7 @@ hipError_t enqueue_step(kw_sim *s) {
     KW_L(KC_ZGRAD, 4, launch_zfused(st, g, c, t, ZM_GRAD, s0, s123));
     KW_L(KC_YINV, 6, launch_ypass(st, g, c, t, s123, 3, true, nullptr, nullptr));
     KW_L(KC_XVEL, 12 + (ms.het[MED_DTRX] ? 3 : 0),
-         launch_xvel(st, g, c, t, s->med, s123, s->buf.u, s->sen, s->counters));
+         launch_xvel(st, g, c, t, s->med, s123, s->buf.u, s->src, s->sen, s->counters));
     KW_L(KC_YFWD, 6, launch_ypass(st, g, c, t, s123, 3, false, nullptr, nullptr));
     KW_L(KC_ZDIV, 6, launch_zfused(st, g, c, t, ZM_DIV, s123, s456));
     KW_L(KC_YINV, 6, launch_ypass(st, g, c, t, s456, 3, true, nullptr, nullptr));
@@ -585,7 +589,8 @@ hipError_t enqueue_step(kw_sim *s) {
         const double med_units = (ms.het[MED_C0SQ] ? 1 : 0) + (ms.het[MED_NL] ? 1 : 0) +
                                  (ms.het[MED_TA] ? 2 : 0);
         KW_L(KC_XEOS, 4 + med_units + sens_units,
-             launch_xeos(st, g, c, t, s->med, s->sen, s->counters, s45, s->buf.rho_total, S[0]));
+             launch_xeos(st, g, c, t, s->med, s->src, s->sen, s->counters, s45, s->buf.rho_total,
+                         S[0]));
     } else {
         float2 *out1[2] = {S[0], nullptr};
         const double med_units = (ms.het[MED_RHO0] ? 1 : 0) + (ms.het[MED_C0SQ] ? 1 : 0) +
@@ -917,7 +922,10 @@ int kw_create(const kw_grid *grid, const kw_medium *medium, const kw_source *sou
             rp[idx / nx + 1]++;
             xp[i] = (int)(idx % nx);
             el[i] = source->element ? source->element[i] : 0;
-            cf[i] = (float)(2.0 * dt / (3.0 * c0_at((size_t)idx) * grid->dx));
+            // mass: dt M_xi per unit drive; force: dt; pressure: the drive itself
+            cf[i] = source->kind == KW_SOURCE_MASS
+                        ? (float)(2.0 * dt / (3.0 * c0_at((size_t)idx) * grid->dx))
+                        : source->kind == KW_SOURCE_FORCE ? (float)dt : 1.0f;
         }
         for (int r = 0; r < rows; ++r) rp[r + 1] += rp[r];
         std::vector<double> ac(cnt.n_elem), as(cnt.n_elem);
@@ -939,6 +947,9 @@ int kw_create(const kw_grid *grid, const kw_medium *medium, const kw_source *sou
         sd.amp_sin = s->at<double>(L.src_as);
         sd.n_elements = cnt.n_elem;
         sd.omega_dt = 2.0 * kPi * source->freq * dt;
+        sd.kind = source->kind;
+        sd.axis = source->kind == KW_SOURCE_FORCE ? source->axis : 0;
+        sd.t_offset = source->kind == KW_SOURCE_MASS ? 0.5 : source->kind == KW_SOURCE_FORCE ? 0.0 : 1.0;
         s->src_flat.resize(ns);
         for (long i = 0; i < ns; ++i) s->src_flat[i] = (int)source->index[i];
         s->src_elem = el;
@@ -1507,6 +1518,8 @@ int kw_adjoint_create(kw_sim *s, const float *weights, int32_t n_steps, void *de
     *out = nullptr;
     if (n_steps < 1) return fail(KW_EINVAL, "n_steps must be >= 1");
     if (s->src_flat.empty()) return fail(KW_EINVAL, "the simulation has no source");
+    if (s->src.kind != KW_SOURCE_MASS)
+        return fail(KW_EINVAL, "the reverse mode covers mass sources only");
     const int n_window = n_steps - s->record_start + 1;
     if (n_window < 1)
         return fail(KW_EINVAL, "no recorded step: record_start %d > n_steps %d", s->record_start,

@@ -117,12 +117,13 @@ __device__ __forceinline__ void stage_table(float2 *dst, const float2 *__restric
     for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
 }
 
-// Drive value s_e of element e in step n, at t = (n + 1/2) dt (the mass
-// source of Eq. (4d)): a_e sin(omega t + phi_e) = a_e cos(phi_e) sin(omega t)
+// Drive value s_e of element e in step n, at t = (n + t_offset) dt (n + 1/2
+// for the mass source of Eq. (4d), n for the force of Eq. (4b), n + 1 for a
+// pressure source): a_e sin(omega t + phi_e) = a_e cos(phi_e) sin(omega t)
 // + a_e sin(phi_e) cos(omega t) in float64, or the sampled signal.
 __device__ __forceinline__ float drive_at(const SourceDev &src, int e, int n) {
     if (src.signal) return (n < src.n_samples) ? src.signal[(size_t)e * src.n_samples + n] : 0.0f;
-    const double th = src.omega_dt * ((double)n + 0.5);
+    const double th = src.omega_dt * ((double)n + src.t_offset);
     return (float)(src.amp_cos[e] * sin(th) + src.amp_sin[e] * cos(th));
 }
 
@@ -524,15 +525,51 @@ __device__ __forceinline__ void row_r2c(const XArgs &a, float2 *__restrict__ row
     const int cupd = Eng::out_count(a.pi, t);                          \
     (void)nx; (void)rbase; (void)cupd;
 
+// Source values of the rows of this block, scattered into a per-row LDS line
+// of nx floats (`fill` where there is no source point).  Returns whether the
+// block has any source point (uniform over the block).
+// Only threads with `worker` set fill the line (one group per row); every
+// thread of the block takes the barriers.
+__device__ __forceinline__ bool scatter_source(const XArgs &a, float *line, int row, bool ok,
+                                               int t, int L, int b, bool worker = true,
+                                               float fill = 0.0f) {
+    const int nx = a.g.nx;
+    int beg = 0, end = 0;
+    if (a.src.row_ptr && ok && worker) {
+        beg = a.src.row_ptr[row];
+        end = a.src.row_ptr[row + 1];
+    }
+    const bool any = __syncthreads_or(end > beg);
+    if (!any) return false;
+    float *mine = line + (size_t)b * nx;
+    if (worker)
+        for (int x = t; x < nx; x += L) mine[x] = fill;
+    __syncthreads();
+    for (int e = beg + t; e < end; e += L)
+        mine[a.src.xpos[e]] = a.src.coef[e] * a.src.drive[a.src.elem[e]];
+    __syncthreads();
+    return true;
+}
+
 // The three velocity components are independent: blockIdx.y selects one.
-// USER: record u at the mask sensor points (the variant with the row scan).
-template <class Eng, bool USER>
+// FL bit 0: record u at the mask sensor points (the variant with the row
+// scan); bit 1: a force source on one component.
+enum { XV_USER = 1, XV_FORCE = 2 };
+template <class Eng, int FL>
 __global__ void __launch_bounds__(512) kw_xvel(XArgs a) {
     KW_XPROLOGUE
     const int iy = rr % a.g.ny, iz = rr / a.g.ny;
     const int xi = blockIdx.y;
     float2 v[E];
     row_c2r<Eng>(a, pick3(a.Sin, xi) + (size_t)rr * M, ok, t, lds, v, tws, tws + M);
+    // force source on this component: dt F per point in the LDS line
+    float *const fline = reinterpret_cast<float *>(sh + (size_t)a.tb * row_pitch(M)) + (size_t)b * nx;
+    bool has_f = false;
+    if constexpr ((FL & XV_FORCE) != 0) {
+        if (xi == a.src.axis)                                        // block-uniform
+            has_f = scatter_source(a, reinterpret_cast<float *>(sh + (size_t)a.tb * row_pitch(M)),
+                                   rr, ok, t, L, b, true);
+    }
     if (ok) {
         float *u = pick3(a.fld, xi);
         const Coef dtr = xi == 0 ? a.m.dtr[0] : xi == 1 ? a.m.dtr[1] : a.m.dtr[2];
@@ -552,12 +589,18 @@ __global__ void __launch_bounds__(512) kw_xvel(XArgs a) {
                 float2 un;
                 un.x = q.x * (q.x * u0.x - d.x * g.x);
                 un.y = q.y * (q.y * u0.y - d.y * g.y);
+                if constexpr ((FL & XV_FORCE) != 0) {
+                    if (has_f) {
+                        un.x += fline[x];
+                        un.y += fline[x + 1];
+                    }
+                }
                 st2(u, i, un);
                 v[m] = un;
             }
         }
     }
-    if constexpr (USER) {
+    if constexpr ((FL & XV_USER) != 0) {
         // u^(n+1/2) is recorded with p^(n+1): step counter n + 1, already advanced
         const int step = *a.cnt.step;
         const int slot = step - a.sen.record_start;
@@ -588,31 +631,6 @@ __global__ void __launch_bounds__(512) kw_xvel(XArgs a) {
         }
     }
     row_r2c<Eng>(a, pick3(a.Sout, xi) + (size_t)rr * M, ok, t, lds, v, tws, tws + M);
-}
-
-// Source values of the rows of this block, scattered into a per-row LDS line
-// of nx floats (zero where there is no source point).  Returns whether the
-// block has any source point (uniform over the block).
-// Only threads with `worker` set fill the line (one group per row); every
-// thread of the block takes the barriers.
-__device__ __forceinline__ bool scatter_source(const XArgs &a, float *line, int row, bool ok,
-                                               int t, int L, int b, bool worker = true) {
-    const int nx = a.g.nx;
-    int beg = 0, end = 0;
-    if (a.src.row_ptr && ok && worker) {
-        beg = a.src.row_ptr[row];
-        end = a.src.row_ptr[row + 1];
-    }
-    const bool any = __syncthreads_or(end > beg);
-    if (!any) return false;
-    float *mine = line + (size_t)b * nx;
-    if (worker)
-        for (int x = t; x < nx; x += L) mine[x] = 0.0f;
-    __syncthreads();
-    for (int e = beg + t; e < end; e += L)
-        mine[a.src.xpos[e]] = a.src.coef[e] * a.src.drive[a.src.elem[e]];
-    __syncthreads();
-    return true;
 }
 
 // Pressure of the rows of this block at the sensor points (mask mode).
@@ -675,6 +693,25 @@ __device__ __forceinline__ void finish_pressure(const XArgs &a, float *line, int
     const int step = *a.cnt.step;
     const bool rec = step >= a.sen.record_start;
     const int cnt = Eng::out_count(a.pi, t);
+    if constexpr (SENS) {
+        // pressure source: p^(n+1) = s at the source points (NaN marks the others)
+        if (a.src.row_ptr && a.src.kind == KW_SOURCE_PRESSURE &&
+            scatter_source(a, line, row, ok, t, L, b, true, __builtin_nanf(""))) {
+            const float *mine = line + (size_t)b * nx;
+            if (ok) {
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    if (m < cnt) {
+                        const int x = 2 * Eng::out_index(a.pi, t, m);
+                        const float s0 = mine[x], s1 = mine[x + 1];
+                        if (s0 == s0) v[m].x = s0;
+                        if (s1 == s1) v[m].y = s1;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
     bool bad = false;
     if (ok) {
 #pragma unroll
@@ -767,10 +804,12 @@ __global__ void __launch_bounds__(512) kw_xden(XArgs a) {
     const float2 *const twp = post_lds ? tws + M : a.t.tw_post;
     stage_table(tws, a.t.tw_x, M);
     if (post_lds) stage_table(tws + M, a.t.tw_post, M);
+    __syncthreads();
     const float dt = a.g.dt;
     const int cupd = Eng::out_count(a.pi, t);
 
-    const bool has_src = scatter_source(a, line, rr, ok, t, L, b, g == 0);
+    const bool has_src = a.src.kind == KW_SOURCE_MASS &&
+                         scatter_source(a, line, rr, ok, t, L, b, g == 0);
     const float *mysrc = line + (size_t)b * nx;
 
     // phase 1: component g (row_c2r ends with a barrier, so the FFT buffers

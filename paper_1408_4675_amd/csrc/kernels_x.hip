@@ -26,9 +26,10 @@ static inline size_t x_lds(const GridDev &g, const LaunchCfg &c, bool line) {
 
 hipError_t launch_xvel(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
                        const Medium &m, float2 *const *S, float *const *u,
-                       const SensorDev &sen, const Counters &cnt) {
+                       const SourceDev &src, const SensorDev &sen, const Counters &cnt) {
     XArgs a = make_xargs(g, c, t);
     a.m = m;
+    a.src = src;
     a.sen = sen;
     a.cnt = cnt;
     for (int i = 0; i < 3; ++i) {
@@ -38,13 +39,14 @@ hipError_t launch_xvel(hipStream_t s, const GridDev &g, const LaunchCfg &c, cons
     }
     dim3 grid((g.rows + c.tb_x - 1) / c.tb_x, 3);
     dim3 block(c.tb_x * c.px.L);
-    if (sen.u_series) {
-        // velocity series at mask sensor points: the variant with the row scan
-        const size_t lds = x_lds(g, c, true);
-        KW_ENGINE_SWITCH(c.eng_x, hipLaunchKernelGGL((kw_xvel<Eng, true>), grid, block, lds, s, a));
-    } else {
-        const size_t lds = x_lds(g, c, false);
-        KW_ENGINE_SWITCH(c.eng_x, hipLaunchKernelGGL((kw_xvel<Eng, false>), grid, block, lds, s, a));
+    const int fl = (sen.u_series ? XV_USER : 0) |
+                   (src.row_ptr && src.kind == KW_SOURCE_FORCE ? XV_FORCE : 0);
+    const size_t lds = x_lds(g, c, fl != 0);
+    switch (fl) {
+    case 0: KW_ENGINE_SWITCH(c.eng_x, hipLaunchKernelGGL((kw_xvel<Eng, 0>), grid, block, lds, s, a)); break;
+    case 1: KW_ENGINE_SWITCH(c.eng_x, hipLaunchKernelGGL((kw_xvel<Eng, 1>), grid, block, lds, s, a)); break;
+    case 2: KW_ENGINE_SWITCH(c.eng_x, hipLaunchKernelGGL((kw_xvel<Eng, 2>), grid, block, lds, s, a)); break;
+    default: KW_ENGINE_SWITCH(c.eng_x, hipLaunchKernelGGL((kw_xvel<Eng, 3>), grid, block, lds, s, a)); break;
     }
     return hipGetLastError();
 }
@@ -78,10 +80,12 @@ hipError_t launch_xden(hipStream_t s, const GridDev &g, const LaunchCfg &c, cons
 }
 
 hipError_t launch_xeos(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
-                       const Medium &m, const SensorDev &sen, const Counters &cnt,
-                       float2 *const *Sin, const float *rho_total, float2 *Sout) {
+                       const Medium &m, const SourceDev &src, const SensorDev &sen,
+                       const Counters &cnt, float2 *const *Sin, const float *rho_total,
+                       float2 *Sout) {
     XArgs a = make_xargs(g, c, t);
     a.m = m;
+    a.src = src;
     a.sen = sen;
     a.cnt = cnt;
     a.Sin[0] = Sin[0];
@@ -90,10 +94,11 @@ hipError_t launch_xeos(hipStream_t s, const GridDev &g, const LaunchCfg &c, cons
     a.Sout[0] = Sout;
     // the per-row line is only needed to pick mask sensor points out of a row
     const bool mask = sen.row_ptr != nullptr && !sen.all_points;
-    const bool extra = sen.p_min != nullptr || sen.harm != nullptr;
+    const bool psrc = src.row_ptr != nullptr && src.kind == KW_SOURCE_PRESSURE;
+    const bool extra = sen.p_min != nullptr || sen.harm != nullptr || psrc;
     dim3 grid((g.rows + c.tb_x - 1) / c.tb_x);
     dim3 block(c.tb_x * c.px.L);
-    const size_t lds = x_lds(g, c, mask);
+    const size_t lds = x_lds(g, c, mask || psrc);
     if (mask || extra) {
         KW_ENGINE_SWITCH(c.eng_x, hipLaunchKernelGGL((kw_xeos<Eng, true>), grid, block, lds, s, a));
     } else {

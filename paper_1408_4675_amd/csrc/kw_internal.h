@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "kw.h"
+
 namespace kw {
 
 constexpr int kMaxPasses = 8;
@@ -76,7 +78,10 @@ struct SourceDev {
     const float *signal;     // optional [n_elements * n_samples]
     int n_samples;
     double omega_dt;         // 2 pi f dt
-    float *drive;            // [n_elements] value of s_e at the current half step
+    float *drive;            // [n_elements] value of s_e in the current step
+    int kind;                // KW_SOURCE_* (mass, force, pressure)
+    int axis;                // velocity component of a force source
+    double t_offset;         // drive time of step n: (n + t_offset) dt
 };
 
 struct SensorDev {
@@ -147,7 +152,11 @@ struct LaunchCfg {
 // of nx floats per row for du of component z, and, when `line`, one more for
 // source values (or mask sensor values in the lossless case)
 inline bool den_needs_line(const Medium &m, const SourceDev &src, const SensorDev &sen) {
-    return src.row_ptr != nullptr || (!m.absorbing && sen.row_ptr != nullptr && !sen.all_points);
+    // a mass source, or (lossless: the density kernel ends with the pressure)
+    // mask sensors or a pressure source
+    return (src.row_ptr != nullptr && src.kind == KW_SOURCE_MASS) ||
+           (!m.absorbing && ((sen.row_ptr != nullptr && !sen.all_points) ||
+                             (src.row_ptr != nullptr && src.kind == KW_SOURCE_PRESSURE)));
 }
 inline size_t den_lds_bytes(int M, int nx, int tb, bool line) {
     const size_t rp = (size_t)M + (M >> 4) + 1;
@@ -205,14 +214,15 @@ hipError_t launch_zfused(hipStream_t s, const GridDev &g, const LaunchCfg &c, co
                          int mode, float2 *const *in, float2 *const *out);
 hipError_t launch_xvel(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
                        const Medium &m, float2 *const *S, float *const *u,
-                       const SensorDev &sen, const Counters &cnt);
+                       const SourceDev &src, const SensorDev &sen, const Counters &cnt);
 hipError_t launch_xden(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
                        const Medium &m, const SourceDev &src, const SensorDev &sen,
                        const Counters &cnt, float2 *const *Sin, float *const *rho,
                        float *rho_total, float2 *const *Sout);
 hipError_t launch_xeos(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
-                       const Medium &m, const SensorDev &sen, const Counters &cnt,
-                       float2 *const *Sin, const float *rho_total, float2 *Sout);
+                       const Medium &m, const SourceDev &src, const SensorDev &sen,
+                       const Counters &cnt, float2 *const *Sin, const float *rho_total,
+                       float2 *Sout);
 // real field -> packed x-spectrum (forward) or back, scaled by `scale`
 hipError_t launch_xfwd(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
                        const float *src, float2 *dst);

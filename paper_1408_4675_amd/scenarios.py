@@ -39,6 +39,11 @@ REC_P_MIN = 64
 REC_HARMONICS = 128
 REC_U_SERIES = 256
 
+# source kinds; the same values are defined in include/kw.h
+SOURCE_MASS = 0
+SOURCE_FORCE = 1
+SOURCE_PRESSURE = 2
+
 # water, the coupling medium of the paper's application (Section 5)
 WATER = dict(c0=1500.0, rho0=1000.0, alpha0=0.75, bona=5.0)
 
@@ -79,13 +84,17 @@ class Medium:
 
 @dataclass
 class Source:
-    """Pressure drive injected as a mass source at the listed grid points."""
+    """Drive at the listed grid points: a pressure injected as a mass source
+    (the default), a force per unit mass on one velocity component, or a
+    pressure imposed on the points (kind)."""
     index: np.ndarray                      # int64, sorted, unique flat indices
     amp: np.ndarray                        # float32 per element [Pa]
     phase: np.ndarray                      # float32 per element [rad]
     freq: float = 1.0e6                    # [Hz]
     element: Optional[np.ndarray] = None   # int32 per point (None -> element 0)
     signal: Optional[np.ndarray] = None    # float32 [n_elements, n_samples]
+    kind: int = 0                          # SOURCE_MASS, SOURCE_FORCE or SOURCE_PRESSURE
+    axis: int = 0                          # velocity component of a force source
 
     @property
     def n_elements(self) -> int:

@@ -65,7 +65,7 @@ class _Marshalled:
             self.source = A.KwSource(idx.size, idx.ctypes.data_as(_P(C.c_int64)),
                                      None if elem is None else elem.ctypes.data_as(_P(C.c_int32)),
                                      amp.size, _fptr(amp), _fptr(ph), s.freq, _fptr(sig),
-                                     0 if sig is None else sig.shape[1])
+                                     0 if sig is None else sig.shape[1], int(s.kind), int(s.axis))
         else:
             self.source = A.KwSource()
         z = sc.sensor

@@ -399,3 +399,26 @@ def test_parity_pmin_harmonics_useries(kw, mask):
     sim2.load(snap)
     for what in (A.KW_REC_P_MIN, A.KW_REC_HARMONICS):
         assert np.array_equal(sim.gather(what, device=False), sim2.gather(what, device=False))
+
+
+# ---------------------------------------------------------------------------
+# source kinds: force on one velocity component, imposed pressure
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kind,axis,absorbing", [(1, 0, True), (1, 1, False), (1, 2, True),
+                                                 (2, 0, True), (2, 0, False)])
+def test_parity_source_kinds(kw, kind, axis, absorbing):
+    A, Simulation = kw
+    steps = 16
+    scen = sc.small_case(40, 18, 20, seed=23, steps=steps, sensor_mask=True, amp=1e3,
+                         absorbing=absorbing, n_elements=3)
+    src = scen.source
+    scale = 2e6 if kind == sc.SOURCE_PRESSURE else 1e6     # Pa, or m/s^2 (dt F ~ 0.02 m/s)
+    scen = scen.replace(source=sc.Source(index=src.index, element=src.element,
+                                         amp=(src.amp / 1e3 * scale).astype(np.float32),
+                                         phase=src.phase, freq=src.freq, kind=kind, axis=axis),
+                        name="kind%d_axis%d_%s" % (kind, axis, "abs" if absorbing else "lossless"))
+    sim, orc = _run_both(kw, scen, steps)
+    errs, tol = compare_outputs(sim, orc, scen, REPORT)
+    for k, e in errs.items():
+        assert e <= tol, (k, e)
