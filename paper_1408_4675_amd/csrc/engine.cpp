@@ -470,6 +470,7 @@ struct kw_sim {
     std::vector<Rec> recs;
     std::vector<hipEvent_t> pool;
     size_t max_lds = 64 * 1024;        // LDS bytes a block may use on this device
+    bool merged_abs = false;           // absorption terms merged (scalar c0^2 tau, c0^2 eta)
     // host copy of the source set-up (for the reverse-mode step)
     std::vector<int> src_flat, src_elem;
     std::vector<float> src_coef;
@@ -584,13 +585,23 @@ hipError_t enqueue_step(kw_sim *s) {
         float2 *s12[2] = {S[1], S[2]};
         float2 *s45[2] = {S[4], S[5]};
         KW_L(KC_YFWD, 4, launch_ypass(st, g, c, t, s12, 2, false, nullptr, nullptr));
-        KW_L(KC_ZABS, 4, launch_zfused(st, g, c, t, ZM_ABS, s12, s45));
-        KW_L(KC_YINV, 4, launch_ypass(st, g, c, t, s45, 2, true, nullptr, nullptr));
         const double med_units = (ms.het[MED_C0SQ] ? 1 : 0) + (ms.het[MED_NL] ? 1 : 0) +
                                  (ms.het[MED_TA] ? 2 : 0);
-        KW_L(KC_XEOS, 4 + med_units + sens_units,
-             launch_xeos(st, g, c, t, s->med, s->src, s->sen, s->counters, s45, s->buf.rho_total,
-                         S[0]));
+        if (s->merged_abs) {
+            // scalar c0^2 tau and c0^2 eta: both terms of Eq. (8) in one spectrum
+            KW_L(KC_ZABS, 3, launch_zfused(st, g, c, t, ZM_ABSM, s12, s45, s->med.ta.scalar,
+                                           s->med.tb.scalar));
+            KW_L(KC_YINV, 2, launch_ypass(st, g, c, t, s45, 1, true, nullptr, nullptr));
+            KW_L(KC_XEOS, 3 + med_units + sens_units,
+                 launch_xeos(st, g, c, t, s->med, s->src, s->sen, s->counters, s45,
+                             s->buf.rho_total, S[0], true));
+        } else {
+            KW_L(KC_ZABS, 4, launch_zfused(st, g, c, t, ZM_ABS, s12, s45));
+            KW_L(KC_YINV, 4, launch_ypass(st, g, c, t, s45, 2, true, nullptr, nullptr));
+            KW_L(KC_XEOS, 4 + med_units + sens_units,
+                 launch_xeos(st, g, c, t, s->med, s->src, s->sen, s->counters, s45,
+                             s->buf.rho_total, S[0]));
+        }
     } else {
         float2 *out1[2] = {S[0], nullptr};
         const double med_units = (ms.het[MED_RHO0] ? 1 : 0) + (ms.het[MED_C0SQ] ? 1 : 0) +
@@ -884,6 +895,7 @@ int kw_create(const kw_grid *grid, const kw_medium *medium, const kw_source *sou
     Medium &md = s->med;
     md.nonlinear = nonlinear;
     md.absorbing = absorbing;
+    s->merged_abs = absorbing && !ms.het[MED_TA];
     {
         auto fill_map = [&](int which, auto fn, Coef &dst) {
             if (ms.het[which]) {
@@ -1294,7 +1306,7 @@ int kw_stats(kw_sim *s, kw_stats_t *out) {
     out->c_ref = s->c_ref;
     out->workspace_bytes = (int64_t)s->L.total;
     out->fft_forward_per_step = s->med.absorbing ? 6 : 4;
-    out->fft_inverse_per_step = s->med.absorbing ? 8 : 6;
+    out->fft_inverse_per_step = s->med.absorbing ? (s->merged_abs ? 7 : 8) : 6;
     out->kernels_per_step = s->kernels_per_step;
     out->n_classes = KC_COUNT;
     for (int i = 0; i < KC_COUNT; ++i) {

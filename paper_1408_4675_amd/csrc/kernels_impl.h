@@ -268,6 +268,7 @@ struct ZArgs {
     FftPlan pf, pi;          // forward plan and the plan of the inverse
     int tb;
     int ntiles;              // column tiles per ky row
+    float sa, sb;            // ABSM: c0^2 tau and -c0^2 eta of a homogeneous medium
 };
 
 // multiplier of output o at (kx index ix (M = Nyquist), ky index iy, kz index iz)
@@ -300,69 +301,39 @@ __device__ __forceinline__ float2 z_operator(const ZArgs &a, int o, int ix, int 
 // transform the two parts are separated with the partner at -kz,
 //   A = (C(kz) + conj C(-kz)) / 2,   B = (C(kz) - conj C(-kz)) / 2i,
 // each gets its own operator, and the results are repacked as A' + i B'.
-template <class Eng, int MODE, int MAXT = 512>
-__global__ void __launch_bounds__(MAXT) kw_zfused(ZArgs a) {
-    constexpr int E = Eng::E;
-    // LDS: nz twiddles, nz z factors, nz wavenumbers kz, then the column tile
-    extern __shared__ float2 lds_all[];
-    float2 *const tws = lds_all;
-    float2 *const dzl = lds_all + a.g.nz;
-    float *const kzl = reinterpret_cast<float *>(lds_all + 2 * a.g.nz);
-    float2 *const sh = lds_all + zpass_table_slots(a.g.nz);
-    const int tid = threadIdx.x;
-    const int b = tid % a.tb, t = tid / a.tb;
-    const int ny = a.g.ny, M = a.g.M;
-    const size_t stride = (size_t)M * ny;
-    const ColLds lds{sh, a.tb, b};
-    const int cin = Eng::in_count(a.pf, t);
-    const int cmid = Eng::out_count(a.pf, t);
-    const int cout = Eng::out_count(a.pi, t);
-    // Each output has its own blocks, which keeps a block to one forward and
-    // one inverse transform and its register use low.  The divergence and
-    // absorption outputs read inputs of their own (blockIdx.y = output).  The
-    // gradient's three outputs read the same input tile: its blocks come in
-    // a 1D grid ordered so that the three blocks of a tile land on the same
-    // XCD (workgroups go round-robin over the 8 XCDs) one after another, and
-    // the second and third reads of the tile hit that XCD's L2.
-    int blk, o;
-    if constexpr (MODE == ZM_GRAD) {
-        const int B = blockIdx.x, q = B >> 3;
-        blk = (q / 3) * 8 + (B & 7);
-        o = q % 3;
-        if (blk >= a.ntiles * a.g.ny) return;          // whole block: padding of the grid
-    } else {
-        blk = blockIdx.x;
-        o = blockIdx.y;
-    }
-    const int f = (MODE == ZM_GRAD) ? 0 : o;
+// Per-block context of the fused z pass (one tile of columns of one ky row).
+struct ZCtx {
+    int t, b, iy, ix, iyk, M;
+    bool ok, pairing;
+    size_t off, stride;
+    ColLds lds;
+    const float2 *tws;
+    const float *kzl;
+    const float2 *dzl;
+};
 
-    const int tile = blk % a.ntiles, iy = blk / a.ntiles;
-    const int col = tile * a.tb + b;
-    const bool ok = col < M;
-    const size_t off = (size_t)iy * M + col;
-    // column 0 of this row (see col0_type): A rows take kx = 0, B rows the
-    // Nyquist kx, and the double rows are split with their kz <-> -kz partner
-    const int c0type = col0_type(iy, ny);
-    const bool pairing = tile == 0 && c0type == C0_DOUBLE;       // block-uniform
-    int ix = ok ? col : 0, iyk = iy;
-    if (col == 0 && c0type != C0_DOUBLE) {
-        ix = (c0type == C0_A) ? 0 : M;
-        iyk = col0_ky(iy, ny);
-    }
-    float2 v[E];
-    if (ok) {
-        const float2 *src = pick3(a.in, f) + off;
+template <class Eng>
+__device__ __forceinline__ void z_load(const ZArgs &a, const ZCtx &c, const float2 *src,
+                                       float2 (&v)[Eng::E]) {
+    constexpr int E = Eng::E;
+    const int cin = Eng::in_count(a.pf, c.t);
+    if (c.ok) {
 #pragma unroll
         for (int m = 0; m < E; ++m)
-            if (m < cin) v[m] = src[(size_t)Eng::in_index(a.pf, t, m) * stride];
+            if (m < cin) v[m] = src[c.off + (size_t)Eng::in_index(a.pf, c.t, m) * c.stride];
     }
-    stage_table(tws, a.t.tw_z, a.g.nz);
-    if constexpr (MODE != ZM_ABS)
-        stage_table(dzl, (MODE == ZM_GRAD || MODE == ZM_GRADT) ? a.t.dpz : a.t.dmz, a.g.nz);
-    for (int i = threadIdx.x; i < a.g.nz; i += blockDim.x) kzl[i] = a.t.kz[i];
-    __syncthreads();
-    Eng::template run<false>(a.pf, tws, t, lds, v);
-    if (pairing && b == 0) {
+}
+
+// forward z transform of v, then the operator `o` of OPMODE times `scale`
+template <class Eng, int OPMODE>
+__device__ __forceinline__ void z_fwd_op(const ZArgs &a, const ZCtx &c, int o, float scale,
+                                         float2 (&v)[Eng::E]) {
+    constexpr int E = Eng::E;
+    const int t = c.t, b = c.b, iy = c.iy, M = c.M;
+    const ColLds &lds = c.lds;
+    const int cmid = Eng::out_count(a.pf, t);
+    Eng::template run<false>(a.pf, c.tws, t, lds, v);
+    if (c.pairing && b == 0) {
         // the raw spectrum of the double row goes to LDS column 0 (free after
         // the transform's trailing barrier) for the pair loop below
 #pragma unroll
@@ -372,8 +343,9 @@ __global__ void __launch_bounds__(MAXT) kw_zfused(ZArgs a) {
 #pragma unroll
     for (int m = 0; m < E; ++m)
         if (m < cmid)
-            v[m] = c_mul(v[m], z_operator<MODE>(a, o, ix, iyk, Eng::out_index(a.pf, t, m), kzl, dzl));
-    if (pairing) {
+            v[m] = c_mul(v[m], c_scale(z_operator<OPMODE>(a, o, c.ix, c.iyk, Eng::out_index(a.pf, t, m),
+                                                          c.kzl, c.dzl), scale));
+    if (c.pairing) {
         // (kz, -kz) pairs of the double row, one pair per iteration and thread,
         // updated in place in LDS (a pair is read and written by one thread)
         __syncthreads();
@@ -384,14 +356,15 @@ __global__ void __launch_bounds__(MAXT) kw_zfused(ZArgs a) {
                 const float2 c1 = lds.ld(iz), c2 = lds.ld(jz);
                 // A(kz) = (C(kz) + conj C(-kz)) / 2, B(kz) = (C(kz) - conj C(-kz)) / 2i
                 const float2 s1 = c_add(c1, c_conj(c2)), d1 = c_sub(c1, c_conj(c2));
-                const float2 A1 = c_scale(s1, 0.5f), B1 = make_float2(0.5f * d1.y, -0.5f * d1.x);
-                const float2 ya = c_mul(A1, z_operator<MODE>(a, o, 0, iy, iz, kzl, dzl));
-                const float2 yb = c_mul(B1, z_operator<MODE>(a, o, M, iy, iz, kzl, dzl));
+                const float2 A1 = c_scale(s1, 0.5f * scale);
+                const float2 B1 = make_float2(0.5f * scale * d1.y, -0.5f * scale * d1.x);
+                const float2 ya = c_mul(A1, z_operator<OPMODE>(a, o, 0, iy, iz, c.kzl, c.dzl));
+                const float2 yb = c_mul(B1, z_operator<OPMODE>(a, o, M, iy, iz, c.kzl, c.dzl));
                 lds.st(iz, make_float2(ya.x - yb.y, ya.y + yb.x));          // ya + i yb
                 if (jz != iz) {
                     // A(-kz) = conj A(kz), B(-kz) = conj B(kz)
-                    const float2 za = c_mul(c_conj(A1), z_operator<MODE>(a, o, 0, iy, jz, kzl, dzl));
-                    const float2 zb = c_mul(c_conj(B1), z_operator<MODE>(a, o, M, iy, jz, kzl, dzl));
+                    const float2 za = c_mul(c_conj(A1), z_operator<OPMODE>(a, o, 0, iy, jz, c.kzl, c.dzl));
+                    const float2 zb = c_mul(c_conj(B1), z_operator<OPMODE>(a, o, M, iy, jz, c.kzl, c.dzl));
                     lds.st(jz, make_float2(za.x - zb.y, za.y + zb.x));
                 }
             }
@@ -404,12 +377,95 @@ __global__ void __launch_bounds__(MAXT) kw_zfused(ZArgs a) {
         }
         __syncthreads();
     }
-    Eng::template run<true>(a.pi, tws, t, lds, v);
-    if (ok) {
-        float2 *dst = pick3(a.out, o) + off;
+}
+
+template <class Eng, int MODE, int MAXT = 512>
+__global__ void __launch_bounds__(MAXT) kw_zfused(ZArgs a) {
+    constexpr int E = Eng::E;
+    // LDS: nz twiddles, nz z factors, nz wavenumbers kz, then the column tile
+    extern __shared__ float2 lds_all[];
+    float2 *const tws = lds_all;
+    float2 *const dzl = lds_all + a.g.nz;
+    float *const kzl = reinterpret_cast<float *>(lds_all + 2 * a.g.nz);
+    float2 *const sh = lds_all + zpass_table_slots(a.g.nz);
+    const int tid = threadIdx.x;
+    const int b = tid % a.tb, t = tid / a.tb;
+    const int ny = a.g.ny, M = a.g.M;
+    const int cout = Eng::out_count(a.pi, t);
+    // Each output has its own blocks, which keeps a block to one forward and
+    // one inverse transform and its register use low.  The divergence and
+    // absorption outputs read inputs of their own (blockIdx.y = output).  The
+    // gradient's three outputs read the same input tile: its blocks come in
+    // a 1D grid ordered so that the three blocks of a tile land on the same
+    // XCD (workgroups go round-robin over the 8 XCDs) one after another, and
+    // the second and third reads of the tile hit that XCD's L2.  The merged
+    // absorption (ABSM) block transforms both inputs and writes one output.
+    int blk, o;
+    if constexpr (MODE == ZM_GRAD) {
+        const int B = blockIdx.x, q = B >> 3;
+        blk = (q / 3) * 8 + (B & 7);
+        o = q % 3;
+        if (blk >= a.ntiles * a.g.ny) return;          // whole block: padding of the grid
+    } else {
+        blk = blockIdx.x;
+        o = blockIdx.y;
+    }
+    const int f = (MODE == ZM_GRAD) ? 0 : o;
+
+    ZCtx c;
+    c.t = t;
+    c.b = b;
+    c.M = M;
+    const int tile = blk % a.ntiles;
+    c.iy = blk / a.ntiles;
+    const int col = tile * a.tb + b;
+    c.ok = col < M;
+    c.stride = (size_t)M * ny;
+    c.off = (size_t)c.iy * M + col;
+    c.lds = ColLds{sh, a.tb, b};
+    c.tws = tws;
+    c.kzl = kzl;
+    c.dzl = dzl;
+    // column 0 of this row (see col0_type): A rows take kx = 0, B rows the
+    // Nyquist kx, and the double rows are split with their kz <-> -kz partner
+    const int c0type = col0_type(c.iy, ny);
+    c.pairing = tile == 0 && c0type == C0_DOUBLE;                  // block-uniform
+    c.ix = c.ok ? col : 0;
+    c.iyk = c.iy;
+    if (col == 0 && c0type != C0_DOUBLE) {
+        c.ix = (c0type == C0_A) ? 0 : M;
+        c.iyk = col0_ky(c.iy, ny);
+    }
+    float2 v[E];
+    z_load<Eng>(a, c, (MODE == ZM_ABSM) ? a.in[0] : pick3(a.in, f), v);
+    stage_table(tws, a.t.tw_z, a.g.nz);
+    if constexpr (MODE != ZM_ABS && MODE != ZM_ABSM)
+        stage_table(dzl, (MODE == ZM_GRAD || MODE == ZM_GRADT) ? a.t.dpz : a.t.dmz, a.g.nz);
+    for (int i = threadIdx.x; i < a.g.nz; i += blockDim.x) kzl[i] = a.t.kz[i];
+    __syncthreads();
+    float2 *dst;
+    if constexpr (MODE == ZM_ABSM) {
+        // sa k^(y-2) FT(in0) + sb k^(y-1) FT(in1), one inverse transform
+        const int cmid = Eng::out_count(a.pf, t);
+        z_fwd_op<Eng, ZM_ABS>(a, c, 0, a.sa, v);
+        float2 acc[E];
+#pragma unroll
+        for (int m = 0; m < E; ++m) acc[m] = v[m];
+        z_load<Eng>(a, c, a.in[1], v);
+        z_fwd_op<Eng, ZM_ABS>(a, c, 1, a.sb, v);
 #pragma unroll
         for (int m = 0; m < E; ++m)
-            if (m < cout) dst[(size_t)Eng::out_index(a.pi, t, m) * stride] = v[m];
+            if (m < cmid) v[m] = c_add(v[m], acc[m]);
+        dst = a.out[0];
+    } else {
+        z_fwd_op<Eng, MODE>(a, c, o, 1.0f, v);
+        dst = pick3(a.out, o);
+    }
+    Eng::template run<true>(a.pi, tws, t, c.lds, v);
+    if (c.ok) {
+#pragma unroll
+        for (int m = 0; m < E; ++m)
+            if (m < cout) dst[c.off + (size_t)Eng::out_index(a.pi, t, m) * c.stride] = v[m];
     }
 }
 
@@ -902,15 +958,18 @@ __global__ void __launch_bounds__(512) kw_xden(XArgs a) {
 }
 
 // SENS: mask sensors, p_min or harmonic sums are recorded (see finish_pressure)
+// MERGED: one input spectrum that already holds ta a + tb b (merged absorption
+// pass of a medium with scalar ta, tb) instead of a and b.
 // Asked to fit six wavefronts per SIMD (80 registers; a few bytes spill):
 // measured faster than five without spills.
-template <class Eng, bool SENS>
+template <class Eng, bool SENS, bool MERGED>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6))) kw_xeos(XArgs a) {
     KW_XPROLOGUE
     float *line = reinterpret_cast<float *>(sh + (size_t)a.tb * row_pitch(M));
     float2 va[E], v[E];
-    row_c2r<Eng>(a, a.Sin[0] + (size_t)rr * M, ok, t, lds, va, tws, tws + M);
-    row_c2r<Eng>(a, a.Sin[1] + (size_t)rr * M, ok, t, lds, v, tws, tws + M);
+    if constexpr (!MERGED)
+        row_c2r<Eng>(a, a.Sin[0] + (size_t)rr * M, ok, t, lds, va, tws, tws + M);
+    row_c2r<Eng>(a, a.Sin[MERGED ? 0 : 1] + (size_t)rr * M, ok, t, lds, v, tws, tws + M);
     if (ok) {
 #pragma unroll
         for (int m = 0; m < E; ++m) {
@@ -918,11 +977,16 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6))) k
                 const size_t i = rbase + 2 * Eng::out_index(a.pi, t, m);
                 const float2 rho = ld2(a.rho_total, i);
                 const float2 c2 = coef2_at(a.m.c0sq, i);
-                const float2 ta = coef2_at(a.m.ta, i);
-                const float2 tb = coef2_at(a.m.tb, i);
                 float2 p;
-                p.x = c2.x * rho.x + ta.x * va[m].x + tb.x * v[m].x;
-                p.y = c2.y * rho.y + ta.y * va[m].y + tb.y * v[m].y;
+                if constexpr (MERGED) {
+                    p.x = c2.x * rho.x + v[m].x;
+                    p.y = c2.y * rho.y + v[m].y;
+                } else {
+                    const float2 ta = coef2_at(a.m.ta, i);
+                    const float2 tb = coef2_at(a.m.tb, i);
+                    p.x = c2.x * rho.x + ta.x * va[m].x + tb.x * v[m].x;
+                    p.y = c2.y * rho.y + ta.y * va[m].y + tb.y * v[m].y;
+                }
                 if (a.m.nonlinear) {
                     const float2 nl = coef2_at(a.m.nl, i);
                     p.x += nl.x * rho.x * rho.x;

@@ -82,7 +82,7 @@ hipError_t launch_xden(hipStream_t s, const GridDev &g, const LaunchCfg &c, cons
 hipError_t launch_xeos(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
                        const Medium &m, const SourceDev &src, const SensorDev &sen,
                        const Counters &cnt, float2 *const *Sin, const float *rho_total,
-                       float2 *Sout) {
+                       float2 *Sout, bool merged) {
     XArgs a = make_xargs(g, c, t);
     a.m = m;
     a.src = src;
@@ -99,10 +99,12 @@ hipError_t launch_xeos(hipStream_t s, const GridDev &g, const LaunchCfg &c, cons
     dim3 grid((g.rows + c.tb_x - 1) / c.tb_x);
     dim3 block(c.tb_x * c.px.L);
     const size_t lds = x_lds(g, c, mask || psrc);
-    if (mask || extra) {
-        KW_ENGINE_SWITCH(c.eng_x, hipLaunchKernelGGL((kw_xeos<Eng, true>), grid, block, lds, s, a));
-    } else {
-        KW_ENGINE_SWITCH(c.eng_x, hipLaunchKernelGGL((kw_xeos<Eng, false>), grid, block, lds, s, a));
+    const int variant = (mask || extra ? 1 : 0) | (merged ? 2 : 0);
+    switch (variant) {
+    case 0: KW_ENGINE_SWITCH(c.eng_x, hipLaunchKernelGGL((kw_xeos<Eng, false, false>), grid, block, lds, s, a)); break;
+    case 1: KW_ENGINE_SWITCH(c.eng_x, hipLaunchKernelGGL((kw_xeos<Eng, true, false>), grid, block, lds, s, a)); break;
+    case 2: KW_ENGINE_SWITCH(c.eng_x, hipLaunchKernelGGL((kw_xeos<Eng, false, true>), grid, block, lds, s, a)); break;
+    default: KW_ENGINE_SWITCH(c.eng_x, hipLaunchKernelGGL((kw_xeos<Eng, true, true>), grid, block, lds, s, a)); break;
     }
     return hipGetLastError();
 }

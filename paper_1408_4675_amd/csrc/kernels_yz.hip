@@ -44,11 +44,16 @@ hipError_t launch_ypass(hipStream_t s, const GridDev &g, const LaunchCfg &c, con
     return hipGetLastError();
 }
 
+static int z_inputs(int mode) {
+    return (mode == ZM_GRAD) ? 1 : (mode == ZM_ABS || mode == ZM_ABSM) ? 2 : 3;
+}
+static int z_outputs(int mode) { return (mode == ZM_ABS) ? 2 : (mode == ZM_ABSM) ? 1 : 3; }
+
 static ZArgs make_zargs(const GridDev &g, const LaunchCfg &c, const Tables &t, int mode,
                         float2 *const *in, float2 *const *out) {
     ZArgs a{};
-    const int nin = (mode == ZM_GRAD) ? 1 : (mode == ZM_ABS) ? 2 : 3;
-    const int nout = (mode == ZM_ABS) ? 2 : 3;
+    const int nin = z_inputs(mode);
+    const int nout = z_outputs(mode);
     for (int i = 0; i < nin; ++i) a.in[i] = in[i];
     for (int i = 0; i < nout; ++i) a.out[i] = out[i];
     a.g = g;
@@ -61,9 +66,17 @@ static ZArgs make_zargs(const GridDev &g, const LaunchCfg &c, const Tables &t, i
 }
 
 hipError_t launch_zfused(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
-                         int mode, float2 *const *in, float2 *const *out) {
-    const ZArgs a = make_zargs(g, c, t, mode, in, out);
-    const int nout = (mode == ZM_ABS) ? 2 : 3;
+                         int mode, float2 *const *in, float2 *const *out, float sa, float sb) {
+    ZArgs a = make_zargs(g, c, t, mode, in, out);
+    a.sa = sa;
+    a.sb = sb;
+    if (mode == ZM_ABSM && a.tb * c.pz.L > 512 && a.tb > 1) {
+        // the merged pass holds two spectra per thread: it does not fit the
+        // registers of a 1024-thread block, so it runs half-width tiles
+        a.tb /= 2;
+        a.ntiles = (g.M + a.tb - 1) / a.tb;
+    }
+    const int nout = z_outputs(mode);
     const int nblk = a.ntiles * g.ny;
     // gradient: 1D grid, XCD-aware order (see kw_zfused), padded to whole groups of 8 tiles
     dim3 grid = (mode == ZM_GRAD) ? dim3((nblk + 7) / 8 * 8 * 3, 1) : dim3(nblk, nout);
@@ -75,6 +88,7 @@ hipError_t launch_zfused(hipStream_t s, const GridDev &g, const LaunchCfg &c, co
         else if (mode == ZM_DIV) hipLaunchKernelGGL((kw_zfused<ENGT, ZM_DIV, MAXT>), grid, block, lds, s, a); \
         else if (mode == ZM_ABS) hipLaunchKernelGGL((kw_zfused<ENGT, ZM_ABS, MAXT>), grid, block, lds, s, a); \
         else if (mode == ZM_DIVT) hipLaunchKernelGGL((kw_zfused<ENGT, ZM_DIVT, MAXT>), grid, block, lds, s, a); \
+        else if (mode == ZM_ABSM) hipLaunchKernelGGL((kw_zfused<ENGT, ZM_ABSM, MAXT>), grid, block, lds, s, a); \
         else hipLaunchKernelGGL((kw_zfused<ENGT, ZM_GRADT, MAXT>), grid, block, lds, s, a);    \
     } while (0)
     if (block.x > 512) {

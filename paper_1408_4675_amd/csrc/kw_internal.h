@@ -183,7 +183,10 @@ inline size_t zcol_lds_bytes(int n, int tb) {
 // DIVT, GRADT: input o, output o multiplied by conj(D-_o kappa) / N and
 // conj(D+_o kappa) / N, the transposes of the real operators of DIV and GRAD
 // (used by the reverse-mode step)
-enum { ZM_GRAD = 0, ZM_DIV = 1, ZM_ABS = 2, ZM_DIVT = 3, ZM_GRADT = 4 };
+// ABSM: ta k^(y-2) / N on input 0 plus tb k^(y-1) / N on input 1, summed into
+// one output (the two absorption terms of Eq. (8) for a medium whose
+// c0^2 tau and c0^2 eta are scalars: one inverse transform instead of two)
+enum { ZM_GRAD = 0, ZM_DIV = 1, ZM_ABS = 2, ZM_DIVT = 3, ZM_GRADT = 4, ZM_ABSM = 5 };
 
 // reverse-mode (adjoint) step state, all device arrays of N floats unless noted
 struct AdjDev {
@@ -211,7 +214,8 @@ hipError_t launch_ypass(hipStream_t s, const GridDev &g, const LaunchCfg &c, con
                         const Counters *prologue, const SourceDev *src,
                         const SensorDev *sen = nullptr);
 hipError_t launch_zfused(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
-                         int mode, float2 *const *in, float2 *const *out);
+                         int mode, float2 *const *in, float2 *const *out, float sa = 1.0f,
+                         float sb = 1.0f);
 hipError_t launch_xvel(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
                        const Medium &m, float2 *const *S, float *const *u,
                        const SourceDev &src, const SensorDev &sen, const Counters &cnt);
@@ -222,7 +226,7 @@ hipError_t launch_xden(hipStream_t s, const GridDev &g, const LaunchCfg &c, cons
 hipError_t launch_xeos(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
                        const Medium &m, const SourceDev &src, const SensorDev &sen,
                        const Counters &cnt, float2 *const *Sin, const float *rho_total,
-                       float2 *Sout);
+                       float2 *Sout, bool merged = false);
 // real field -> packed x-spectrum (forward) or back, scaled by `scale`
 hipError_t launch_xfwd(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
                        const float *src, float2 *dst);
