@@ -77,6 +77,13 @@ BAD = [
     ("unsorted source", dict(unsorted=True)),
     ("source out of grid", dict(src_oob=True)),
     ("series without index", dict(series_all=True)),
+    ("velocity series without index", dict(useries_all=True)),
+    ("unknown source kind", dict(kind=7)),
+    ("force axis out of range", dict(kind=1, axis=3)),
+    ("too many harmonics", dict(harmonics=17)),
+    ("harmonics without frequency", dict(harmonics=2, no_source=True)),
+    ("unknown record bit", dict(record=1 << 12)),
+    ("record_start 0", dict(record_start=0)),
 ]
 
 
@@ -97,6 +104,19 @@ def test_validation_rejects_bad_inputs(lib, name, kw):
         scen.source.index = np.array([0, 10 ** 9], np.int64)
     if kw.get("series_all"):
         scen.sensor = sc.Sensor(record=sc.REC_P_SERIES, index=None, series_capacity=4)
+    if kw.get("useries_all"):
+        scen.sensor = sc.Sensor(record=sc.REC_U_SERIES, index=None, series_capacity=4)
+    if "kind" in kw:
+        scen.source.kind = kw["kind"]
+        scen.source.axis = kw.get("axis", 0)
+    if "harmonics" in kw:
+        scen.sensor = sc.Sensor(record=sc.REC_HARMONICS, n_harmonics=kw["harmonics"])
+    if kw.get("no_source"):
+        scen.source = None
+    if "record" in kw:
+        scen.sensor = sc.Sensor(record=kw["record"])
+    if "record_start" in kw:
+        scen.sensor = sc.Sensor(record=sc.REC_P_MAX, record_start=kw["record_start"])
     assert _ws(lib, scen) == 0
     assert lib.kw_last_error().decode()
     m = _Marshalled(scen)

@@ -422,3 +422,48 @@ def test_parity_source_kinds(kw, kind, axis, absorbing):
     errs, tol = compare_outputs(sim, orc, scen, REPORT)
     for k, e in errs.items():
         assert e <= tol, (k, e)
+
+
+# ---------------------------------------------------------------------------
+# edge cases: smallest and odd grids, the widest x row, degenerate set-ups
+# ---------------------------------------------------------------------------
+
+EDGE = [(4, 4, 4), (6, 5, 4), (8, 9, 5), (10, 15, 25), (2048, 4, 4), (4, 6, 2 * 3 * 5 * 5)]
+
+
+@pytest.mark.parametrize("shape", EDGE, ids=["%dx%dx%d" % s for s in EDGE])
+def test_parity_edge_shapes(kw, shape):
+    """Minimum sizes (two-point x spectra), odd y and z lengths (no Nyquist row
+    or plane), the longest x row (1024-point x transforms) and a mixed-radix z."""
+    nx, ny, nz = shape
+    scen = sc.small_case(nx, ny, nz, seed=31, heterogeneous=True, nonlinear=True,
+                         absorbing=True, pml=1, steps=8, sensor_mask=False)
+    sim, orc = _run_both(kw, scen, 8)
+    errs, tol = compare_outputs(sim, orc, scen, REPORT)
+    for k, e in errs.items():
+        assert e <= tol, (k, e)
+
+
+def test_degenerate_setups(kw):
+    A, Simulation = kw
+    base = sc.small_case(24, 10, 12, seed=3, steps=6)
+    _banner("degenerate set-ups")
+    # zero drive: every field stays exactly zero
+    src = base.source
+    zero = base.replace(source=sc.Source(index=src.index, amp=np.zeros(1, np.float32),
+                                         phase=src.phase, freq=src.freq))
+    sim = Simulation(zero)
+    sim.step(6)
+    assert not np.any(sim.gather(A.KW_REC_P_FINAL, device=False))
+    assert not np.any(sim.gather(A.KW_REC_U_FINAL, device=False))
+    # no source and no sensor: steps run, the final fields are readable
+    sim = Simulation(base.replace(source=None, sensor=sc.Sensor(record=0)))
+    sim.step(3)
+    assert not np.any(sim.get_field(A.KW_FIELD_P))
+    # zero steps, then recorded quantities of an empty window
+    sim = Simulation(base.replace(sensor=sc.Sensor(record=sc.REC_P_RMS | sc.REC_P_MAX,
+                                                   record_start=100)))
+    sim.step(0)
+    sim.step(4)
+    assert not np.any(sim.gather(A.KW_REC_P_RMS, device=False))
+    assert np.all(np.isneginf(sim.gather(A.KW_REC_P_MAX, device=False)))
