@@ -174,3 +174,43 @@ def lookup(grid) -> Dict[int, Tuple[List[int], int]]:
                 out[axis] = (list(e["radices"]), int(e.get("tile", 0)))
                 break
     return out
+
+
+def tune_table(sizes, steps: int = 3, out: Optional[str] = None, verbose: bool = True) -> Dict:
+    """Tune every axis for each cubic size in `sizes` (for lengths above 256
+    on a grid whose other two axes are 64 points, one axis at a time) and
+    return {key: choice}; with `out`, also write it as JSON (the format of the
+    shipped tables)."""
+    from . import scenarios as sc
+    arch = _arch()
+    table = {}
+    for n in sizes:
+        if n <= 256:
+            jobs = [(sc.small_case(n, n, n, seed=0, steps=8), (0, 1, 2))]
+        else:
+            jobs = []
+            for axis in range(3):
+                shape = [64, 64, 64]
+                shape[axis] = n
+                jobs.append((sc.small_case(*shape, seed=0, steps=8), (axis,)))
+        for scen, axes in jobs:
+            res = tune(scen, axes=axes, steps=steps, verbose=verbose, save=False)
+            for axis, (sched, tile, ms) in res.items():
+                table[key(axis, lengths(scen.grid)[axis], arch)] = dict(radices=sched, tile=tile,
+                                                                         ms=round(ms, 5))
+            if verbose:
+                print("tuned n=%d axes %s" % (n, axes), flush=True)
+    if out:
+        with open(out, "w") as fh:
+            json.dump(table, fh, indent=1, sort_keys=True)
+    return table
+
+
+if __name__ == "__main__":
+    import argparse
+    ap = argparse.ArgumentParser(prog="python -m paper_1408_4675_amd.autotune")
+    ap.add_argument("--sizes", type=int, nargs="+", default=[64, 96, 128, 160, 192, 256, 1024])
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--out", default=None, help="write the table here (JSON)")
+    a = ap.parse_args()
+    tune_table(a.sizes, a.steps, a.out)
