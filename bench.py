@@ -142,6 +142,41 @@ def host_info():
     return dict(nproc=os.cpu_count(), ram_gib=mem_gb)
 
 
+# The paper's own CPU-cluster throughput, derived from its run times (context
+# only: other hardware, other precision of the statement, I/O included).
+PAPER_CONTEXT = [
+    dict(what="largest benchmark, 4096x2048x2048 points, 25,000 steps projected at about 4.5 "
+              "days on 1024 cores (Section 4.5)",
+         grid_point_updates_per_s=1.1e9, cores=1024),
+    dict(what="kidney application, 2048x1536x1536 points, 19,800 steps in 31 h 20 min on 768 "
+              "cores including I/O and restarts (Section 5)",
+         grid_point_updates_per_s=8.48e8, cores=768),
+]
+
+
+def cpu_scaling(sizes=(64, 128, 256), steps=3):
+    """The FP64 oracle at several sizes, on all host cores and on one core
+    (median step time after one warm-up step)."""
+    from oracle import Oracle
+    from paper_1408_4675_amd import scenarios as sc
+    out = []
+    for n in sizes:
+        scen = sc.tissue_bowl(seed=0, n=n, steps=steps + 1)
+        for workers in (os.cpu_count(), 1):
+            o = Oracle(scen, workers=workers)
+            o.step(1)
+            ts = []
+            for _ in range(steps):
+                t0 = time.perf_counter()
+                o.step(1)
+                ts.append(time.perf_counter() - t0)
+            med = float(np.median(ts))
+            out.append(dict(n=n, cores=workers, s_per_step=round(med, 4),
+                            grid_point_updates_per_s=round(scen.grid.npts / med, 1)))
+            log("oracle %d^3 on %d cores: %.3f s per step" % (n, workers, med))
+    return dict(points=out, host=host_info())
+
+
 def cpu_baseline(scen, warm=1, steps=2):
     import numpy as np
     from oracle import Oracle
@@ -251,6 +286,9 @@ def main():
     ap.add_argument("--serving", type=int, default=0, metavar="N",
                     help="instead of the step benchmark, serve the first N requests of the "
                          "Poisson trace (20/s, 64^3-256^3 tissue) batched and one at a time")
+    ap.add_argument("--cpu-scaling", action="store_true",
+                    help="instead of the step benchmark, time the FP64 oracle at 64^3, 128^3 and "
+                         "256^3 on all host cores and on one core")
     ap.add_argument("--adjoint", action="store_true",
                     help="instead of the step benchmark, time the gradient of the focusing "
                          "objective (128^3 tissue, 64-element bowl, 600 steps)")
@@ -259,6 +297,12 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+
+    if args.cpu_scaling:
+        # host only: no GPU needed
+        print(json.dumps(dict(metric="FP64 oracle grid-point updates/s on the host",
+                              oracle=cpu_scaling(), paper_context=PAPER_CONTEXT)), flush=True)
+        return
 
     import torch
     from paper_1408_4675_amd import scenarios as sc
@@ -330,6 +374,7 @@ def main():
                                 per_class=bper)
         except Exception as e:   # report, but keep the headline line
             out["large"] = dict(error=str(e))
+    out["paper_context"] = PAPER_CONTEXT
     if not args.no_cpu:
         log("timing the CPU oracle baseline")
         # about 12 s of FP64 work on a 16-core host (1.4 s per step)
