@@ -205,12 +205,17 @@ def serving_bench(n_requests, rate=20.0, seed=0):
                           sizes=list(sc.SERVING_SIZES), steps="300-1500",
                           offered_point_updates_per_s=rate * float(np.mean(
                               [r.scenario.grid.npts * r.scenario.steps for r in reqs]))))
+    def progress(tag):
+        return lambda r: log("%s: request %d done (%.1f s after arrival)" % (tag, r.rid, r.latency))
+
     log("batched")
     srv = Server(max_active=8, chunk_steps=64)
-    out["batched"] = summarize(srv.run(reqs, on_done=lambda r: log("done %d" % r.rid)))
+    out["batched"] = summarize(srv.run(reqs, on_done=progress("batched")))
     out["batched"]["peak_active"] = srv.peak_active
+    log("batched: %s" % json.dumps(out["batched"]))
     log("fifo")
-    out["fifo"] = summarize(run_fifo(reqs))
+    out["fifo"] = summarize(run_fifo(reqs, on_done=progress("fifo")))
+    log("fifo: %s" % json.dumps(out["fifo"]))
     cap = out["batched"]["point_updates_per_s"]
     work = float(np.mean([r.scenario.grid.npts * r.scenario.steps for r in reqs]))
     lam = 0.7 * cap / work
@@ -218,8 +223,9 @@ def serving_bench(n_requests, rate=20.0, seed=0):
     reqs2 = sc.serving_trace(seed=seed, n_requests=n_requests, rate=lam, medium_pool=2)
     out["sustainable_rate_per_s"] = lam
     srv2 = Server(max_active=8, chunk_steps=64)
-    out["batched_at_sustainable"] = summarize(srv2.run(reqs2))
-    out["fifo_at_sustainable"] = summarize(run_fifo(reqs2))
+    out["batched_at_sustainable"] = summarize(srv2.run(reqs2, on_done=progress("batched, sustainable")))
+    log("batched at sustainable: %s" % json.dumps(out["batched_at_sustainable"]))
+    out["fifo_at_sustainable"] = summarize(run_fifo(reqs2, on_done=progress("fifo, sustainable")))
     return out
 
 

@@ -151,7 +151,7 @@ class Server:
 
 
 def run_fifo(requests: Sequence[Request], keep_outputs: bool = False,
-             device: str = "cuda") -> List[Result]:
+             device: str = "cuda", on_done: Optional[Callable] = None) -> List[Result]:
     """Baseline: one request at a time in arrival order (each waits for the
     previous one to finish)."""
     A.load()
@@ -170,6 +170,8 @@ def run_fifo(requests: Sequence[Request], keep_outputs: bool = False,
         sim.close()
         results.append(Result(r.rid, r.scenario.grid.npts, r.scenario.steps, r.arrival, start,
                               fin, outs))
+        if on_done:
+            on_done(results[-1])
     return results
 
 
