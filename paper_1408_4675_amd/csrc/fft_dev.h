@@ -242,30 +242,52 @@ __device__ __forceinline__ void dft_rt(int R, float2 (&v)[RM]) {
 }
 
 // --- LDS addressing ------------------------------------------------------------
+// Orders the LDS accesses of one wavefront.  Its lanes run in lockstep and the
+// LDS serves one wavefront's requests in order, so a transform whose threads
+// all lie in one wavefront needs no s_barrier between its passes: only the
+// compiler must keep the accesses on their side of this point.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Column batches (y and z passes): element n of transform b at sh[n * tb + b];
 // consecutive lanes hold consecutive b, so every access is bank-conflict free
-// once tb >= 16.
+// once tb >= 16.  A column's threads span wavefronts: block barriers.
 struct ColLds {
     float2 *sh;
     int tb, b;
     __device__ __forceinline__ float2 ld(int n) const { return sh[n * tb + b]; }
     __device__ __forceinline__ void st(int n, float2 x) const { sh[n * tb + b] = x; }
+    __device__ __forceinline__ void sync() const { __syncthreads(); }
 };
 // Row batches (x passes): transform b occupies a padded row; one pad slot per
-// 16 elements spreads the strided Stockham writes over the banks.
+// 16 elements spreads the strided Stockham writes over the banks.  `wave`:
+// the L threads of a row are lanes of one wavefront (L divides the wavefront
+// size and rows start at multiples of L), so the passes synchronise only the
+// wavefront; the flag is uniform over the block.
 struct RowLds {
     float2 *sh;
     int base;
+    bool wave;
     __device__ __forceinline__ float2 ld(int n) const { return sh[base + n + (n >> 4)]; }
     __device__ __forceinline__ void st(int n, float2 x) const { sh[base + n + (n >> 4)] = x; }
+    __device__ __forceinline__ void sync() const {
+        if (wave) wave_sync();
+        else __syncthreads();
+    }
 };
+// Whether the rows of L threads of a block lie within wavefronts
+__device__ __forceinline__ bool rows_in_waves(int L) { return (warpSize % L) == 0; }
 __host__ __device__ inline int row_pitch(int n) { return n + (n >> 4) + 1; }
 
 // --- the pass loop -----------------------------------------------------------
 // On entry v[r] (r < radix[0]) holds x[t + r n/radix[0]] for t < n/radix[0].
 // On exit v[r] (r < radix[np-1]) holds X[t + r n/radix[np-1]] for t < n/radix[np-1].
-// Every thread of the block must call this (it contains barriers); the
-// trailing barrier makes the LDS buffer free for reuse on return.
+// Every thread of the block must call this (it contains barriers, of the block
+// or of the wavefront, see RowLds); the trailing one makes the LDS buffer free
+// for reuse by the same threads on return.
 template <bool INV, int RM, class Lds>
 __device__ __forceinline__ void fft_run(const FftPlan &P, const float2 *__restrict__ tw, int t,
                                         const Lds &lds, float2 (&v)[RM]) {
@@ -275,13 +297,13 @@ __device__ __forceinline__ void fft_run(const FftPlan &P, const float2 *__restri
         const int nb = P.n / R;
         const bool act = t < nb;
         if (p > 0) {
-            __syncthreads();
+            lds.sync();
             if (act) {
 #pragma unroll
                 for (int r = 0; r < RM; ++r)
                     if (r < R) v[r] = lds.ld(t + r * nb);
             }
-            __syncthreads();
+            lds.sync();
         }
         if (act) {
             const int k = t % Ns;
@@ -305,7 +327,7 @@ __device__ __forceinline__ void fft_run(const FftPlan &P, const float2 *__restri
         }
         Ns *= R;
     }
-    __syncthreads();
+    lds.sync();
 }
 
 
@@ -359,10 +381,10 @@ __device__ __forceinline__ void fft_fixed(const FftPlan &P, const float2 *__rest
     for (int p = 0; p < P.np; ++p) {
         const int R = plan_radix(P, p);
         if (p > 0) {
-            __syncthreads();
+            lds.sync();
 #pragma unroll
             for (int m = 0; m < E; ++m) v[m] = lds.ld(t + m * L);
-            __syncthreads();
+            lds.sync();
         }
         const int st = P.n / (Ns * R);
         const bool write = p < P.np - 1;
@@ -376,7 +398,7 @@ __device__ __forceinline__ void fft_fixed(const FftPlan &P, const float2 *__rest
         }
         Ns *= R;
     }
-    __syncthreads();
+    lds.sync();
 }
 
 // Engine policies used by the kernels.  `in_*` is the register layout of the

@@ -538,7 +538,7 @@ __device__ __forceinline__ void row_r2c(const XArgs &a, float2 *__restrict__ row
 #pragma unroll
     for (int m = 0; m < E; ++m)
         if (m < cout) lds.st(Eng::out_index(a.pf, t, m), v[m]);
-    __syncthreads();
+    lds.sync();
     if (ok) {
 #pragma unroll
         for (int m = 0; m < E; ++m) {
@@ -559,7 +559,7 @@ __device__ __forceinline__ void row_r2c(const XArgs &a, float2 *__restrict__ row
             }
         }
     }
-    __syncthreads();
+    lds.sync();
 }
 
 #define KW_XPROLOGUE                                                   \
@@ -576,7 +576,7 @@ __device__ __forceinline__ void row_r2c(const XArgs &a, float2 *__restrict__ row
     const bool ok = row < a.g.rows;                                    \
     const int rr = ok ? row : 0;                                       \
     const int M = a.g.M, nx = a.g.nx;                                  \
-    const RowLds lds{sh, b * row_pitch(M)};                            \
+    const RowLds lds{sh, b * row_pitch(M), rows_in_waves(L)};          \
     const size_t rbase = (size_t)rr * nx;                              \
     const int cupd = Eng::out_count(a.pi, t);                          \
     (void)nx; (void)rbase; (void)cupd;
@@ -812,148 +812,118 @@ __device__ __forceinline__ void finish_pressure(const XArgs &a, float *line, int
     row_r2c<Eng>(a, a.Sout[0] + (size_t)(ok ? row : 0) * M, ok, t, lds, v, twx, twp);
 }
 
-// Density update.  The three split components are coupled only through
-// rho = sum rho_xi and sum du_xi, so a block runs them side by side: thread
-// group g (g = 0, 1, 2) transforms and updates component g of the block's tb
-// rows, and then group 0 transforms rho0 sum du and group 1 stores rho and
-// transforms it (group 2 takes the same barriers without storing).  Without
-// absorption group 1 evaluates the equation of state instead.  Each thread
-// holds one component's values, as in kw_xvel.
-// The groups exchange only what the others need: group 0 keeps du_0 and group
-// 1 keeps rho_1 in registers; rho_0, du_1 and rho_2 go to the (then idle) FFT
-// buffers of groups 0, 1 and 2, and du_2 to a line of its own.
-// LDS: [3 groups][tb rows] FFT buffers, [tb] du_2 lines (twiddles during the transforms),
-// [tb] source lines.
-// ABS (= a.m.absorbing) is a template parameter: the lossless tail (equation
-// of state, sensors, pressure transform) would otherwise set the register
-// count of the absorbing kernel too.
-template <class Eng, bool ABS>
+// Density update (Eqs. (4c), (8) with the split-field PML of Eq. (6)), and
+// what follows from rho within the step.  One thread group per row (as in
+// kw_xvel) runs the three split components one after the other -- inverse x
+// transform of du_xi, update of rho_xi -- and keeps the sums over the
+// components in registers: sum rho (rho, stored for the pressure kernel) and
+// sum du.  With absorption it then transforms rho0 sum du (into Sout[0]) and
+// rho (into Sout[1]) for the absorption pass; without, it evaluates the
+// equation of state and finishes the pressure like kw_xeos.
+// The transforms of a row synchronise only its wavefront (RowLds), so the
+// wavefronts of a block run independently between the few block barriers
+// (twiddle staging, the source scatter, sensors).
+// SRC: a mass source (values scattered once into the still idle FFT buffers
+// and kept in registers); ABS = a.m.absorbing.  Both are template parameters
+// so that the common paths do not carry the registers of the others.
+template <class Eng, bool ABS, bool SRC>
 __global__ void __launch_bounds__(512) kw_xden(XArgs a) {
-    constexpr int E = Eng::E;
-    extern __shared__ float2 lds_all[];
-    float2 *const sh = lds_all;
-    const int L = a.pf.L;
-    const int M = a.g.M, nx = a.g.nx, tb = a.tb;
-    const int tid = threadIdx.x;
-    const int g = tid / (tb * L);
-    const int rem = tid - g * tb * L;
-    const int b = rem / L, t = rem % L;
-    const int row = blockIdx.x * tb + b;
-    const bool ok = row < a.g.rows;
-    const int rr = ok ? row : 0;
+    KW_XPROLOGUE
     const int iy = rr % a.g.ny, iz = rr / a.g.ny;
-    const size_t rbase = (size_t)rr * nx;
-    const int RP = row_pitch(M);
-    const RowLds lds{sh, (g * tb + b) * RP};
-    float2 *buf0 = sh + (size_t)b * RP;                      // row b's buffer of group 0
-    float2 *buf1 = sh + (size_t)(tb + b) * RP;
-    float2 *buf2 = sh + (size_t)(2 * tb + b) * RP;
-    float2 *du2 = sh + (size_t)3 * tb * RP + (size_t)b * M;   // nx floats per row
-    float *line = reinterpret_cast<float *>(sh + (size_t)3 * tb * RP + (size_t)tb * M);
-    // The twiddle tables (tw_x, and tw_post when there are two lines or more)
-    // are staged in the du_2 lines, which are free during both transforms:
-    // once for the inverse transforms of phase 1 (du_2 is written after them)
-    // and again for the forward transforms of phase 2 (after du_2 has been
-    // read).  This keeps the LDS of three 10-row blocks within a CU.
-    float2 *const tws = sh + (size_t)3 * tb * RP;
-    const bool post_lds = tb >= 2;                                    // block-uniform
-    const float2 *const twp = post_lds ? tws + M : a.t.tw_post;
-    stage_table(tws, a.t.tw_x, M);
-    if (post_lds) stage_table(tws + M, a.t.tw_post, M);
-    __syncthreads();
     const float dt = a.g.dt;
-    const int cupd = Eng::out_count(a.pi, t);
-
-    const bool has_src = a.src.kind == KW_SOURCE_MASS &&
-                         scatter_source(a, line, rr, ok, t, L, b, g == 0);
-    const float *mysrc = line + (size_t)b * nx;
-
-    // phase 1: component g (row_c2r ends with a barrier, so the FFT buffers
-    // are free for the exchange afterwards)
-    float2 v[E];
-    row_c2r<Eng>(a, pick3(a.Sin, g) + (size_t)rr * M, ok, t, lds, v, tws, twp);
-    {
-        float *rho = pick3(a.fld, g);
-        const float qy = a.t.pml_y[iy], qz = a.t.pml_z[iz];
-        float2 *xrho = (g == 0) ? buf0 : buf2;
+    // source values and sensor lines alias the FFT buffers; every use lies
+    // between block barriers, outside the transforms
+    float *const line = reinterpret_cast<float *>(sh);
+    float2 sv[SRC ? E : 1];
+    bool has_src = false;
+    if constexpr (SRC) {
+        has_src = scatter_source(a, line, rr, ok, t, L, b);
+        if (has_src) {
+            const float *mine = line + (size_t)b * nx;
 #pragma unroll
-        for (int m = 0; m < E; ++m) {
-            if (m < cupd) {
-                const int n = Eng::out_index(a.pi, t, m);
-                const int x = 2 * n;
-                const size_t i = rbase + x;
-                float2 nw = make_float2(0.0f, 0.0f);
-                const float2 d = v[m];
-                if (ok) {
+            for (int m = 0; m < E; ++m) {
+                const int x = 2 * Eng::out_index(a.pi, t, m);
+                sv[m] = (m < cupd) ? make_float2(mine[x], mine[x + 1]) : make_float2(0.f, 0.f);
+            }
+            __syncthreads();
+        }
+    }
+    float2 sr[E], sd[ABS ? E : 1];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        sr[m] = make_float2(0.f, 0.f);
+        if constexpr (ABS) sd[m] = make_float2(0.f, 0.f);
+    }
+    const float qy = a.t.pml_y[iy], qz = a.t.pml_z[iz];
+#pragma unroll 1
+    for (int g = 0; g < 3; ++g) {
+        // salt = 0, unknown to the compiler: it makes the element indices
+        // depend on g, so that they are recomputed in every iteration rather
+        // than hoisted out of the loop and held in registers across it
+        const int salt = g * a.zero;
+        const int ts = t + salt;
+        const RowLds ldg{sh, lds.base + salt, lds.wave};
+        float2 v[E];
+        row_c2r<Eng>(a, pick3(a.Sin, g) + (size_t)rr * M, ok, ts, ldg, v, tws, tws + M, salt);
+        float *rho = pick3(a.fld, g);
+        if (ok) {
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                if (m < cupd) {
+                    const int x = 2 * Eng::out_index(a.pi, ts, m);
+                    const size_t i = rbase + x;
                     float2 q;
                     if (g == 0) q = make_float2(a.t.pml_x[x], a.t.pml_x[x + 1]);
                     else if (g == 1) q = make_float2(qy, qy);
                     else q = make_float2(qz, qz);
                     const float2 r0 = coef2_at(a.m.rho0, i);
                     const float2 old = ld2(rho, i);
+                    const float2 d = v[m];
+                    float2 nw;
                     nw.x = q.x * (q.x * old.x - dt * r0.x * d.x);
                     nw.y = q.y * (q.y * old.y - dt * r0.y * d.y);
                     if (a.m.nonlinear) {
                         nw.x = nw.x / (1.0f + 2.0f * dt * d.x);
                         nw.y = nw.y / (1.0f + 2.0f * dt * d.y);
                     }
-                    if (has_src) {
-                        nw.x += mysrc[x];
-                        nw.y += mysrc[x + 1];
+                    if constexpr (SRC) {
+                        if (has_src) nw = c_add(nw, sv[m]);
                     }
                     st2(rho, i, nw);
-                }
-                if (g == 1) {
-                    buf1[n] = d;
-                    v[m] = nw;
-                } else {
-                    xrho[n] = nw;
-                    if (g == 2) du2[n] = d;
+                    sr[m] = c_add(sr[m], nw);
+                    if constexpr (ABS) sd[m] = c_add(sd[m], d);
                 }
             }
         }
     }
-    __syncthreads();
-
-    // phase 2: sums over the components (group 0: sum du, group 1: rho)
+    float2 v[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-        if (m < cupd) {
-            const int n = Eng::out_index(a.pi, t, m);
-            const size_t i = rbase + 2 * n;
-            if (g == 0) {
-                if constexpr (ABS) {
-                    const float2 s = c_add(c_add(v[m], buf1[n]), du2[n]);
-                    const float2 r0 = coef2_at(a.m.rho0, i);
-                    v[m] = make_float2(r0.x * s.x, r0.y * s.y);
+        v[m] = make_float2(0.f, 0.f);
+        if (m < cupd && ok) {
+            const size_t i = rbase + 2 * Eng::out_index(a.pi, t, m);
+            const float2 r = sr[m];
+            if constexpr (ABS) {
+                const float2 r0 = coef2_at(a.m.rho0, i);
+                v[m] = make_float2(r0.x * sd[m].x, r0.y * sd[m].y);
+                st2(a.rho_total, i, r);
+            } else {
+                const float2 c2 = coef2_at(a.m.c0sq, i);
+                float2 pp = make_float2(c2.x * r.x, c2.y * r.y);
+                if (a.m.nonlinear) {
+                    const float2 nl = coef2_at(a.m.nl, i);
+                    pp.x += nl.x * r.x * r.x;
+                    pp.y += nl.y * r.y * r.y;
                 }
-            } else if (g == 1) {
-                const float2 r = c_add(c_add(v[m], buf0[n]), buf2[n]);
-                if constexpr (ABS) {
-                    v[m] = r;
-                    if (ok) st2(a.rho_total, i, r);
-                } else {
-                    const float2 c2 = coef2_at(a.m.c0sq, i);
-                    float2 pp = make_float2(c2.x * r.x, c2.y * r.y);
-                    if (a.m.nonlinear) {
-                        const float2 nl = coef2_at(a.m.nl, i);
-                        pp.x += nl.x * r.x * r.x;
-                        pp.y += nl.y * r.y * r.y;
-                    }
-                    v[m] = pp;
-                }
+                v[m] = pp;
             }
         }
     }
-    __syncthreads();   // the forward transforms below overwrite the exchanged values
-    stage_table(tws, a.t.tw_x, M);
-    if (post_lds) stage_table(tws + M, a.t.tw_post, M);
-    __syncthreads();
     if constexpr (ABS) {
-        float2 *dst = (g == 0) ? a.Sout[0] : a.Sout[1];
-        row_r2c<Eng>(a, dst + (size_t)rr * M, ok && g < 2, t, lds, v, tws, twp);
+        row_r2c<Eng>(a, a.Sout[0] + (size_t)rr * M, ok, t, lds, v, tws, tws + M);
+        row_r2c<Eng>(a, a.Sout[1] + (size_t)rr * M, ok, t, lds, sr, tws, tws + M);
     } else {
-        finish_pressure<Eng>(a, line, rr, ok && g == 1, t, L, b, lds, v, tws, twp);
+        finish_pressure<Eng>(a, line, rr, ok, t, L, b, lds, v, tws, tws + M);
     }
 }
 

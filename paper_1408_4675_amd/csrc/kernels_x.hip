@@ -67,14 +67,16 @@ hipError_t launch_xden(hipStream_t s, const GridDev &g, const LaunchCfg &c, cons
     a.Sout[0] = Sout[0];
     a.Sout[1] = Sout[1];
     a.rho_total = rho_total;
-    a.tb = c.tb_den;
-    dim3 grid((g.rows + c.tb_den - 1) / c.tb_den);
-    dim3 block(3 * c.tb_den * c.px.L);
-    const size_t lds = den_lds_bytes(g.M, g.nx, c.tb_den, den_needs_line(m, src, sen));
-    if (m.absorbing) {
-        KW_ENGINE_SWITCH(c.eng_x, hipLaunchKernelGGL((kw_xden<Eng, true>), grid, block, lds, s, a));
-    } else {
-        KW_ENGINE_SWITCH(c.eng_x, hipLaunchKernelGGL((kw_xden<Eng, false>), grid, block, lds, s, a));
+    dim3 grid((g.rows + c.tb_x - 1) / c.tb_x);
+    dim3 block(c.tb_x * c.px.L);
+    // source values and sensor lines use the FFT buffers (2 M + 2 floats a row)
+    const size_t lds = x_lds(g, c, false);
+    const int variant = (m.absorbing ? 1 : 0) | (src.row_ptr && src.kind == KW_SOURCE_MASS ? 2 : 0);
+    switch (variant) {
+    case 0: KW_ENGINE_SWITCH(c.eng_x, hipLaunchKernelGGL((kw_xden<Eng, false, false>), grid, block, lds, s, a)); break;
+    case 1: KW_ENGINE_SWITCH(c.eng_x, hipLaunchKernelGGL((kw_xden<Eng, true, false>), grid, block, lds, s, a)); break;
+    case 2: KW_ENGINE_SWITCH(c.eng_x, hipLaunchKernelGGL((kw_xden<Eng, false, true>), grid, block, lds, s, a)); break;
+    default: KW_ENGINE_SWITCH(c.eng_x, hipLaunchKernelGGL((kw_xden<Eng, true, true>), grid, block, lds, s, a)); break;
     }
     return hipGetLastError();
 }
