@@ -260,7 +260,7 @@ __global__ void __launch_bounds__(MAXT) kw_ypass(YArgs a) {
 // (z-pass modes ZM_* are defined in kw_internal.h)
 
 struct ZArgs {
-    int zero;                // always 0 (see the salt in kw_xvel)
+    int zero;                // always 0 (see the salt of the gradient in kw_zfused)
     const float2 *in[3];
     float2 *out[3];
     GridDev g;
@@ -324,15 +324,14 @@ __device__ __forceinline__ void z_load(const ZArgs &a, const ZCtx &c, const floa
     }
 }
 
-// forward z transform of v, then the operator `o` of OPMODE times `scale`
+// v (a forward z spectrum) times the operator `o` of OPMODE times `scale`
 template <class Eng, int OPMODE>
-__device__ __forceinline__ void z_fwd_op(const ZArgs &a, const ZCtx &c, int o, float scale,
-                                         float2 (&v)[Eng::E]) {
+__device__ __forceinline__ void z_op(const ZArgs &a, const ZCtx &c, int o, float scale,
+                                     float2 (&v)[Eng::E]) {
     constexpr int E = Eng::E;
     const int t = c.t, b = c.b, iy = c.iy, M = c.M;
     const ColLds &lds = c.lds;
     const int cmid = Eng::out_count(a.pf, t);
-    Eng::template run<false>(a.pf, c.tws, t, lds, v);
     if (c.pairing && b == 0) {
         // the raw spectrum of the double row goes to LDS column 0 (free after
         // the transform's trailing barrier) for the pair loop below
@@ -379,6 +378,14 @@ __device__ __forceinline__ void z_fwd_op(const ZArgs &a, const ZCtx &c, int o, f
     }
 }
 
+// forward z transform of v, then the operator `o` of OPMODE times `scale`
+template <class Eng, int OPMODE>
+__device__ __forceinline__ void z_fwd_op(const ZArgs &a, const ZCtx &c, int o, float scale,
+                                         float2 (&v)[Eng::E]) {
+    Eng::template run<false>(a.pf, c.tws, c.t, c.lds, v);
+    z_op<Eng, OPMODE>(a, c, o, scale, v);
+}
+
 template <class Eng, int MODE, int MAXT = 512>
 __global__ void __launch_bounds__(MAXT) kw_zfused(ZArgs a) {
     constexpr int E = Eng::E;
@@ -392,24 +399,16 @@ __global__ void __launch_bounds__(MAXT) kw_zfused(ZArgs a) {
     const int b = tid % a.tb, t = tid / a.tb;
     const int ny = a.g.ny, M = a.g.M;
     const int cout = Eng::out_count(a.pi, t);
-    // Each output has its own blocks, which keeps a block to one forward and
-    // one inverse transform and its register use low.  The divergence and
-    // absorption outputs read inputs of their own (blockIdx.y = output).  The
-    // gradient's three outputs read the same input tile: its blocks come in
-    // a 1D grid ordered so that the three blocks of a tile land on the same
-    // XCD (workgroups go round-robin over the 8 XCDs) one after another, and
-    // the second and third reads of the tile hit that XCD's L2.  The merged
-    // absorption (ABSM) block transforms both inputs and writes one output.
-    int blk, o;
-    if constexpr (MODE == ZM_GRAD) {
-        const int B = blockIdx.x, q = B >> 3;
-        blk = (q / 3) * 8 + (B & 7);
-        o = q % 3;
-        if (blk >= a.ntiles * a.g.ny) return;          // whole block: padding of the grid
-    } else {
-        blk = blockIdx.x;
-        o = blockIdx.y;
-    }
+    // The divergence and absorption outputs read inputs of their own: each
+    // output has its own blocks (blockIdx.y = output), which keeps a block to
+    // one forward and one inverse transform and its register use low.  The
+    // gradient's three outputs share one input: its block transforms the tile
+    // once and runs the three operators and inverse transforms from the kept
+    // spectrum (the pass is bound by vector ALU work, and this saves two of
+    // the six transforms of a tile).  The merged absorption (ABSM) block
+    // transforms both inputs and writes one output.
+    const int blk = blockIdx.x;
+    const int o = (MODE == ZM_GRAD) ? 0 : blockIdx.y;
     const int f = (MODE == ZM_GRAD) ? 0 : o;
 
     ZCtx c;
@@ -443,6 +442,33 @@ __global__ void __launch_bounds__(MAXT) kw_zfused(ZArgs a) {
         stage_table(dzl, (MODE == ZM_GRAD || MODE == ZM_GRADT) ? a.t.dpz : a.t.dmz, a.g.nz);
     for (int i = threadIdx.x; i < a.g.nz; i += blockDim.x) kzl[i] = a.t.kz[i];
     __syncthreads();
+    if constexpr (MODE == ZM_GRAD) {
+        Eng::template run<false>(a.pf, c.tws, t, c.lds, v);
+        float2 S[E];
+#pragma unroll
+        for (int m = 0; m < E; ++m) S[m] = v[m];
+#pragma unroll 1
+        for (int oo = 0; oo < 3; ++oo) {
+            // salt = 0, unknown to the compiler: the indices of this output are
+            // recomputed rather than hoisted out of the loop into registers
+            const int salt = oo * a.zero;
+            ZCtx cs = c;
+            cs.t = t + salt;
+            cs.off = c.off + salt;
+            cs.lds.b = b + salt;
+#pragma unroll
+            for (int m = 0; m < E; ++m) v[m] = S[m];
+            z_op<Eng, ZM_GRAD>(a, cs, oo, 1.0f, v);
+            Eng::template run<true>(a.pi, tws + salt, cs.t, cs.lds, v);
+            float2 *const dst = pick3(a.out, oo);
+            if (c.ok) {
+#pragma unroll
+                for (int m = 0; m < E; ++m)
+                    if (m < cout) dst[cs.off + (size_t)Eng::out_index(a.pi, cs.t, m) * c.stride] = v[m];
+            }
+        }
+        return;
+    }
     float2 *dst;
     if constexpr (MODE == ZM_ABSM) {
         // sa k^(y-2) FT(in0) + sb k^(y-1) FT(in1), one inverse transform

@@ -70,16 +70,16 @@ hipError_t launch_zfused(hipStream_t s, const GridDev &g, const LaunchCfg &c, co
     ZArgs a = make_zargs(g, c, t, mode, in, out);
     a.sa = sa;
     a.sb = sb;
-    if (mode == ZM_ABSM && a.tb * c.pz.L > 512 && a.tb > 1) {
-        // the merged pass holds two spectra per thread: it does not fit the
-        // registers of a 1024-thread block, so it runs half-width tiles
+    if ((mode == ZM_ABSM || mode == ZM_GRAD) && a.tb * c.pz.L > 512 && a.tb > 1) {
+        // the merged absorption and the gradient hold two spectra per thread:
+        // they do not fit the registers of a 1024-thread block, so they run
+        // half-width tiles
         a.tb /= 2;
         a.ntiles = (g.M + a.tb - 1) / a.tb;
     }
-    const int nout = z_outputs(mode);
-    const int nblk = a.ntiles * g.ny;
-    // gradient: 1D grid, XCD-aware order (see kw_zfused), padded to whole groups of 8 tiles
-    dim3 grid = (mode == ZM_GRAD) ? dim3((nblk + 7) / 8 * 8 * 3, 1) : dim3(nblk, nout);
+    // one block per tile and output (the gradient's block writes all three)
+    const int nout = (mode == ZM_GRAD) ? 1 : z_outputs(mode);
+    dim3 grid(a.ntiles * g.ny, nout);
     dim3 block(a.tb * c.pz.L);
     size_t lds = zcol_lds_bytes(g.nz, a.tb);
 #define KW_ZMODES(ENGT, MAXT)                                                                  \
