@@ -688,6 +688,11 @@ int pick_tiles(kw_sim *s, int tile_y, int tile_z) {
     if ((rc = check_tb("z pass", c.tb_z, c.pz.L, zcol_lds_bytes(g.nz, c.tb_z), wide_z,
                        s->max_lds)) != KW_OK)
         return rc;
+    // the column passes address an element of their tile by a 32-bit byte offset
+    const uint64_t zlane = ((uint64_t)c.pz.L * g.M * g.ny + c.tb_z) * 8;
+    if (zlane >= (1ull << 32))
+        return fail(KW_EUNSUPPORTED, "z pass: tile offsets of %llu bytes exceed 32 bits",
+                    (unsigned long long)zlane);
     return KW_OK;
 }
 

@@ -255,11 +255,17 @@ __device__ __forceinline__ void wave_sync() {
 // Column batches (y and z passes): element n of transform b at sh[n * tb + b];
 // consecutive lanes hold consecutive b, so every access is bank-conflict free
 // once tb >= 16.  A column's threads span wavefronts: block barriers.
+// ld2/st2(n0, d): element n0 + d with d uniform over the block, so that only
+// n0 * tb is a per-lane product (24-bit, full rate) and d * tb is scalar.
 struct ColLds {
     float2 *sh;
     int tb, b;
-    __device__ __forceinline__ float2 ld(int n) const { return sh[n * tb + b]; }
-    __device__ __forceinline__ void st(int n, float2 x) const { sh[n * tb + b] = x; }
+    __device__ __forceinline__ float2 ld(int n) const { return sh[__umul24(n, tb) + b]; }
+    __device__ __forceinline__ void st(int n, float2 x) const { sh[__umul24(n, tb) + b] = x; }
+    __device__ __forceinline__ float2 ld2(int n0, int d) const { return sh[__umul24(n0, tb) + b + d * tb]; }
+    __device__ __forceinline__ void st2(int n0, int d, float2 x) const {
+        sh[__umul24(n0, tb) + b + d * tb] = x;
+    }
     __device__ __forceinline__ void sync() const { __syncthreads(); }
 };
 // Row batches (x passes): transform b occupies a padded row; one pad slot per
@@ -273,6 +279,8 @@ struct RowLds {
     bool wave;
     __device__ __forceinline__ float2 ld(int n) const { return sh[base + n + (n >> 4)]; }
     __device__ __forceinline__ void st(int n, float2 x) const { sh[base + n + (n >> 4)] = x; }
+    __device__ __forceinline__ float2 ld2(int n0, int d) const { return ld(n0 + d); }
+    __device__ __forceinline__ void st2(int n0, int d, float2 x) const { st(n0 + d, x); }
     __device__ __forceinline__ void sync() const {
         if (wave) wave_sync();
         else __syncthreads();
@@ -301,18 +309,18 @@ __device__ __forceinline__ void fft_run(const FftPlan &P, const float2 *__restri
             if (act) {
 #pragma unroll
                 for (int r = 0; r < RM; ++r)
-                    if (r < R) v[r] = lds.ld(t + r * nb);
+                    if (r < R) v[r] = lds.ld2(t, r * nb);
             }
             lds.sync();
         }
         if (act) {
             const int k = t % Ns;
             if (Ns > 1) {
-                const int st = P.n / (Ns * R);
+                const int kst = __umul24(k, P.n / (Ns * R));
 #pragma unroll
                 for (int r = 1; r < RM; ++r) {
                     if (r < R) {
-                        const float2 w = tw[k * r * st];
+                        const float2 w = tw[kst * r];
                         v[r] = INV ? c_mulc(v[r], w) : c_mul(v[r], w);
                     }
                 }
@@ -322,7 +330,7 @@ __device__ __forceinline__ void fft_run(const FftPlan &P, const float2 *__restri
                 const int base = (t - k) * R + k;
 #pragma unroll
                 for (int r = 0; r < RM; ++r)
-                    if (r < R) lds.st(base + r * Ns, v[r]);
+                    if (r < R) lds.st2(base, r * Ns, v[r]);
             }
         }
         Ns *= R;
@@ -348,9 +356,10 @@ struct FixedBfly {
             const int j = t + Bi * L;
             const int k = j & (Ns - 1);
             if (Ns > 1) {
+                const int kst = __umul24(k, st);
 #pragma unroll
                 for (int r = 1; r < R; ++r) {
-                    const float2 w = tw[k * r * st];
+                    const float2 w = tw[kst * r];
                     v[Bi + r * B] = INV ? c_mulc(v[Bi + r * B], w) : c_mul(v[Bi + r * B], w);
                 }
             }
@@ -358,7 +367,7 @@ struct FixedBfly {
             if (write) {
                 const int base = (j - k) * R + k;
 #pragma unroll
-                for (int r = 0; r < R; ++r) lds.st(base + r * Ns, v[Bi + r * B]);
+                for (int r = 0; r < R; ++r) lds.st2(base, r * Ns, v[Bi + r * B]);
             }
             FixedBfly<E, R, INV, Bi + 1>::run(v, t, L, Ns, st, tw, lds, write);
         }
@@ -383,7 +392,7 @@ __device__ __forceinline__ void fft_fixed(const FftPlan &P, const float2 *__rest
         if (p > 0) {
             lds.sync();
 #pragma unroll
-            for (int m = 0; m < E; ++m) v[m] = lds.ld(t + m * L);
+            for (int m = 0; m < E; ++m) v[m] = lds.ld2(t, m * L);
             lds.sync();
         }
         const int st = P.n / (Ns * R);
@@ -423,6 +432,11 @@ struct EngGeneric {
     __device__ static __forceinline__ int out_index(const FftPlan &P, int t, int m) {
         return t + m * (P.n / plan_radix(P, P.np - 1));
     }
+    // index distance between consecutive m of the input / output layout
+    __device__ static __forceinline__ int in_step(const FftPlan &P) { return P.n / plan_radix(P, 0); }
+    __device__ static __forceinline__ int out_step(const FftPlan &P) {
+        return P.n / plan_radix(P, P.np - 1);
+    }
     template <bool INV, class Lds>
     __device__ static __forceinline__ void run(const FftPlan &P, const float2 *tw, int t,
                                                const Lds &lds, float2 (&v)[RM]) {
@@ -441,6 +455,8 @@ struct EngFixed {
     __device__ static __forceinline__ int out_index(const FftPlan &P, int t, int m) {
         return t + m * P.L;
     }
+    __device__ static __forceinline__ int in_step(const FftPlan &P) { return P.L; }
+    __device__ static __forceinline__ int out_step(const FftPlan &P) { return P.L; }
     template <bool INV, class Lds>
     __device__ static __forceinline__ void run(const FftPlan &P, const float2 *tw, int t,
                                                const Lds &lds, float2 (&v)[EE]) {

@@ -56,6 +56,50 @@ __device__ __forceinline__ float2 ld2(const float *p, size_t i) {
 __device__ __forceinline__ void st2(float *p, size_t i, float2 v) {
     *reinterpret_cast<float2 *>(p + i) = v;
 }
+// Element at a 32-bit byte offset from p, p uniform over the wavefront.  p
+// is read into scalar registers (readfirstlane) and accessed as global memory,
+// so that each access is one instruction with a scalar base and a vector
+// offset: no 64-bit address arithmetic per element (left to itself the
+// compiler re-associates base and offset into 64-bit vector multiply-adds).
+// The column passes keep their per-lane offsets below 4 GiB (checked when a
+// simulation is set up).
+typedef __attribute__((address_space(1))) char gchar;
+__device__ __forceinline__ gchar *global_uniform(const void *p) {
+    const uint64_t u = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    return reinterpret_cast<gchar *>(((uint64_t)hi << 32) | lo);
+}
+typedef float vf2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float2 ld_at(const float2 *p, uint32_t off) {
+    const vf2 x = *reinterpret_cast<const __attribute__((address_space(1))) vf2 *>(global_uniform(p) + off);
+    return make_float2(x.x, x.y);
+}
+__device__ __forceinline__ void st_at(float2 *p, uint32_t off, float2 v) {
+    vf2 x;
+    x.x = v.x;
+    x.y = v.y;
+    *reinterpret_cast<__attribute__((address_space(1))) vf2 *>(global_uniform(p) + off) = x;
+}
+// A pair of real grid values (x, x + 1) of a row of an x-pass block: element
+// index u, uniform over the block, plus a per-lane byte offset l (row within
+// the block and x), so that one lane offset serves every field and element
+// of a thread.
+struct XPos {
+    size_t u;
+    uint32_t l;
+};
+__device__ __forceinline__ float2 ld2(const float *p, XPos e) {
+    return ld_at(reinterpret_cast<const float2 *>(p + e.u), e.l);
+}
+__device__ __forceinline__ void st2(float *p, XPos e, float2 v) {
+    st_at(reinterpret_cast<float2 *>(p + e.u), e.l, v);
+}
+__device__ __forceinline__ float2 coef2_at(const Coef &c, XPos e) {
+    if (c.map) return ld2(c.map, e);
+    return make_float2(c.scalar, c.scalar);
+}
+
 // select one of three values without indexing the argument array at run time
 // (a run-time index into a by-value kernel argument forces it into scratch)
 template <class T>
@@ -160,8 +204,11 @@ __global__ void __launch_bounds__(MAXT) kw_ypass(YArgs a) {
     const int b = tid % a.tb, t = tid / a.tb;
     const int col = blockIdx.x * a.tb + b;
     const bool ok = col < a.M;
-    float2 *base = pick3(a.f, (int)blockIdx.z) + (size_t)blockIdx.y * a.ny * a.M + col;
-    const size_t stride = a.M;
+    // element (row t + m step, column col) of this block's tile: uniform base
+    // base + m step M, lane offset (t M + b) elements
+    float2 *const base = pick3(a.f, (int)blockIdx.z) + (size_t)blockIdx.y * a.ny * a.M +
+                         (size_t)blockIdx.x * a.tb;
+    const uint32_t lane = (uint32_t)(t * a.M + b) * 8u;
 
     if (a.prologue && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0) {
         const int n = *a.cnt.step;
@@ -180,9 +227,10 @@ __global__ void __launch_bounds__(MAXT) kw_ypass(YArgs a) {
     const ColLds lds{sh, a.tb, b};
     const int cin = Eng::in_count(a.plan, t);
     if (ok) {
+        const size_t jump = (size_t)Eng::in_step(a.plan) * a.M;
 #pragma unroll
         for (int m = 0; m < E; ++m)
-            if (m < cin) v[m] = base[(size_t)Eng::in_index(a.plan, t, m) * stride];
+            if (m < cin) v[m] = ld_at(base + m * jump, lane);
     }
     stage_table(tws, a.tw, ny);
     __syncthreads();
@@ -248,9 +296,10 @@ __global__ void __launch_bounds__(MAXT) kw_ypass(YArgs a) {
         __syncthreads();
     }
     if (ok) {
+        const size_t jump = (size_t)Eng::out_step(a.plan) * a.M;
 #pragma unroll
         for (int m = 0; m < E; ++m)
-            if (m < cout) base[(size_t)Eng::out_index(a.plan, t, m) * stride] = v[m];
+            if (m < cout) st_at(base + m * jump, lane, v[m]);
     }
 }
 
@@ -305,7 +354,9 @@ __device__ __forceinline__ float2 z_operator(const ZArgs &a, int o, int ix, int 
 struct ZCtx {
     int t, b, iy, ix, iyk, M;
     bool ok, pairing;
-    size_t off, stride;
+    size_t off;              // element offset of the tile (uniform): iy M + first column
+    size_t stride;           // element distance of consecutive z
+    uint32_t lane;           // byte offset of (z = t, column b) from the tile
     ColLds lds;
     const float2 *tws;
     const float *kzl;
@@ -318,9 +369,26 @@ __device__ __forceinline__ void z_load(const ZArgs &a, const ZCtx &c, const floa
     constexpr int E = Eng::E;
     const int cin = Eng::in_count(a.pf, c.t);
     if (c.ok) {
+        const float2 *const base = src + c.off;
+        const size_t jump = (size_t)Eng::in_step(a.pf) * c.stride;
 #pragma unroll
         for (int m = 0; m < E; ++m)
-            if (m < cin) v[m] = src[c.off + (size_t)Eng::in_index(a.pf, c.t, m) * c.stride];
+            if (m < cin) v[m] = ld_at(base + m * jump, c.lane);
+    }
+}
+
+// store of the inverse transform's output layout
+template <class Eng>
+__device__ __forceinline__ void z_store(const ZArgs &a, const ZCtx &c, float2 *dst,
+                                        const float2 (&v)[Eng::E]) {
+    constexpr int E = Eng::E;
+    const int cout = Eng::out_count(a.pi, c.t);
+    if (c.ok) {
+        float2 *const base = dst + c.off;
+        const size_t jump = (size_t)Eng::out_step(a.pi) * c.stride;
+#pragma unroll
+        for (int m = 0; m < E; ++m)
+            if (m < cout) st_at(base + m * jump, c.lane, v[m]);
     }
 }
 
@@ -398,7 +466,6 @@ __global__ void __launch_bounds__(MAXT) kw_zfused(ZArgs a) {
     const int tid = threadIdx.x;
     const int b = tid % a.tb, t = tid / a.tb;
     const int ny = a.g.ny, M = a.g.M;
-    const int cout = Eng::out_count(a.pi, t);
     // The divergence and absorption outputs read inputs of their own: each
     // output has its own blocks (blockIdx.y = output), which keeps a block to
     // one forward and one inverse transform and its register use low.  The
@@ -420,7 +487,8 @@ __global__ void __launch_bounds__(MAXT) kw_zfused(ZArgs a) {
     const int col = tile * a.tb + b;
     c.ok = col < M;
     c.stride = (size_t)M * ny;
-    c.off = (size_t)c.iy * M + col;
+    c.off = (size_t)c.iy * M + (size_t)tile * a.tb;
+    c.lane = (uint32_t)((size_t)t * c.stride + b) * 8u;
     c.lds = ColLds{sh, a.tb, b};
     c.tws = tws;
     c.kzl = kzl;
@@ -454,18 +522,13 @@ __global__ void __launch_bounds__(MAXT) kw_zfused(ZArgs a) {
             const int salt = oo * a.zero;
             ZCtx cs = c;
             cs.t = t + salt;
-            cs.off = c.off + salt;
+            cs.lane = c.lane + salt;
             cs.lds.b = b + salt;
 #pragma unroll
             for (int m = 0; m < E; ++m) v[m] = S[m];
             z_op<Eng, ZM_GRAD>(a, cs, oo, 1.0f, v);
             Eng::template run<true>(a.pi, tws + salt, cs.t, cs.lds, v);
-            float2 *const dst = pick3(a.out, oo);
-            if (c.ok) {
-#pragma unroll
-                for (int m = 0; m < E; ++m)
-                    if (m < cout) dst[cs.off + (size_t)Eng::out_index(a.pi, cs.t, m) * c.stride] = v[m];
-            }
+            z_store<Eng>(a, cs, pick3(a.out, oo), v);
         }
         return;
     }
@@ -488,11 +551,7 @@ __global__ void __launch_bounds__(MAXT) kw_zfused(ZArgs a) {
         dst = pick3(a.out, o);
     }
     Eng::template run<true>(a.pi, tws, t, c.lds, v);
-    if (c.ok) {
-#pragma unroll
-        for (int m = 0; m < E; ++m)
-            if (m < cout) dst[c.off + (size_t)Eng::out_index(a.pi, t, m) * c.stride] = v[m];
-    }
+    z_store<Eng>(a, c, dst, v);
 }
 
 // ---------------------------------------------------------------------------
@@ -519,8 +578,11 @@ struct XArgs {
 
 // c2r: packed spectrum row -> v[m] = x[2n] + i x[2n+1], n = out_index(pi, t, m)
 // (unnormalised; the result is nx times the inverse DFT)
+// S: the spectrum array; the row is row b of this block (rows of a block are
+// consecutive: element k of it lies at a block-uniform address plus a lane
+// offset, and M - k likewise)
 template <class Eng>
-__device__ __forceinline__ void row_c2r(const XArgs &a, const float2 *__restrict__ row, bool ok,
+__device__ __forceinline__ void row_c2r(const XArgs &a, const float2 *S, int b, bool ok,
                                         int t, const RowLds &lds, float2 (&v)[Eng::E],
                                         const float2 *twx, const float2 *twp, int salt = 0) {
     constexpr int E = Eng::E;
@@ -528,18 +590,23 @@ __device__ __forceinline__ void row_c2r(const XArgs &a, const float2 *__restrict
     const float2 *tw_post = twp + salt;
     const int cin = Eng::in_count(a.pi, t);
     if (ok) {
+        const float2 *const blk = S + (size_t)blockIdx.x * a.tb * M;
+        const int step = Eng::in_step(a.pi) + salt;   // (salt: see kw_xden)
+        // k = t + m step: blk + m step + (b M + t);  M - k: blk + M - (m + 1) step + (b M + step - t)
+        const uint32_t l1 = (uint32_t)(b * M + t) * 8u;
+        const uint32_t l2 = (uint32_t)(b * M + step - t) * 8u;
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             if (m < cin) {
                 const int k = Eng::in_index(a.pi, t, m);
-                const float2 P = row[k];
+                const float2 P = ld_at(blk + m * step, l1);
                 float2 xk, xm;
                 if (k == 0) {
                     xk = make_float2(P.x, 0.0f);
                     xm = make_float2(P.y, 0.0f);
                 } else {
                     xk = P;
-                    xm = row[M - k];
+                    xm = ld_at(blk + M - (m + 1) * step, l2);
                 }
                 const float2 A = make_float2(xk.x + xm.x, xk.y - xm.y);        // xk + conj(xm)
                 const float2 D = make_float2(xk.x - xm.x, xk.y + xm.y);        // xk - conj(xm)
@@ -553,11 +620,14 @@ __device__ __forceinline__ void row_c2r(const XArgs &a, const float2 *__restrict
 
 // r2c: v[m] = x[2n] + i x[2n+1], n = in_index(pf, t, m)  ->  packed spectrum row
 template <class Eng>
-__device__ __forceinline__ void row_r2c(const XArgs &a, float2 *__restrict__ row, bool ok, int t,
+__device__ __forceinline__ void row_r2c(const XArgs &a, float2 *S, int b, bool ok, int t,
                                         const RowLds &lds, float2 (&v)[Eng::E],
                                         const float2 *twx, const float2 *twp, int salt = 0) {
     constexpr int E = Eng::E;
     const int M = a.g.M;
+    float2 *const blk = S + (size_t)blockIdx.x * a.tb * M;
+    const int ostep = Eng::out_step(a.pf);
+    const uint32_t l1 = (uint32_t)(b * M + t) * 8u;
     const float2 *tw_post = twp + salt;
     Eng::template run<false>(a.pf, twx + salt, t, lds, v);
     const int cout = Eng::out_count(a.pf, t);
@@ -581,7 +651,7 @@ __device__ __forceinline__ void row_r2c(const XArgs &a, float2 *__restrict__ row
                     const float2 c = c_mul(tw_post[k], Bh);
                     out = make_float2(A.x + c.y, A.y - c.x);     // A - i w^k B
                 }
-                row[k] = out;
+                st_at(blk + m * ostep, l1, out);
             }
         }
     }
@@ -605,7 +675,10 @@ __device__ __forceinline__ void row_r2c(const XArgs &a, float2 *__restrict__ row
     const RowLds lds{sh, b * row_pitch(M), rows_in_waves(L)};          \
     const size_t rbase = (size_t)rr * nx;                              \
     const int cupd = Eng::out_count(a.pi, t);                          \
-    (void)nx; (void)rbase; (void)cupd;
+    /* real values x = 2 n, n = t + m step of row b: see XPos */       \
+    const size_t xrow0 = (size_t)blockIdx.x * a.tb * nx;               \
+    const uint32_t xlane = (uint32_t)(b * nx + 2 * t) * 4u;            \
+    (void)nx; (void)rbase; (void)cupd; (void)xrow0; (void)xlane;
 
 // Source values of the rows of this block, scattered into a per-row LDS line
 // of nx floats (`fill` where there is no source point).  Returns whether the
@@ -643,7 +716,7 @@ __global__ void __launch_bounds__(512) kw_xvel(XArgs a) {
     const int iy = rr % a.g.ny, iz = rr / a.g.ny;
     const int xi = blockIdx.y;
     float2 v[E];
-    row_c2r<Eng>(a, pick3(a.Sin, xi) + (size_t)rr * M, ok, t, lds, v, tws, tws + M);
+    row_c2r<Eng>(a, pick3(a.Sin, xi), b, ok, t, lds, v, tws, tws + M);
     // force source on this component: dt F per point in the LDS line
     float *const fline = reinterpret_cast<float *>(sh + (size_t)a.tb * row_pitch(M)) + (size_t)b * nx;
     bool has_f = false;
@@ -660,7 +733,7 @@ __global__ void __launch_bounds__(512) kw_xvel(XArgs a) {
         for (int m = 0; m < E; ++m) {
             if (m < cupd) {
                 const int x = 2 * Eng::out_index(a.pi, t, m);
-                const size_t i = rbase + x;
+                const XPos i{xrow0 + 2 * (size_t)m * Eng::out_step(a.pi), xlane};
                 float2 q;
                 if (xi == 0) q = make_float2(a.t.pml_sx[x], a.t.pml_sx[x + 1]);
                 else if (xi == 1) q = make_float2(qy, qy);
@@ -712,7 +785,7 @@ __global__ void __launch_bounds__(512) kw_xvel(XArgs a) {
             }
         }
     }
-    row_r2c<Eng>(a, pick3(a.Sout, xi) + (size_t)rr * M, ok, t, lds, v, tws, tws + M);
+    row_r2c<Eng>(a, pick3(a.Sout, xi), b, ok, t, lds, v, tws, tws + M);
 }
 
 // Pressure of the rows of this block at the sensor points (mask mode).
@@ -772,6 +845,8 @@ __device__ __forceinline__ void finish_pressure(const XArgs &a, float *line, int
     constexpr int E = Eng::E;
     const int M = a.g.M, nx = a.g.nx;
     const size_t rbase = (size_t)(ok ? row : 0) * nx;
+    const size_t xrow0 = (size_t)blockIdx.x * a.tb * nx;
+    const uint32_t xlane = (uint32_t)(b * nx + 2 * t) * 4u;
     const int step = *a.cnt.step;
     const bool rec = step >= a.sen.record_start;
     const int cnt = Eng::out_count(a.pi, t);
@@ -802,7 +877,7 @@ __device__ __forceinline__ void finish_pressure(const XArgs &a, float *line, int
                 const float2 p = v[m];
                 bad |= !(__builtin_isfinite(p.x) && __builtin_isfinite(p.y));
                 if (rec && a.sen.all_points) {
-                    const size_t i = rbase + 2 * Eng::out_index(a.pi, t, m);
+                    const XPos i{xrow0 + 2 * (size_t)m * Eng::out_step(a.pi), xlane};
                     if (a.sen.p_max) {
                         const float2 mx = ld2(a.sen.p_max, i);
                         st2(a.sen.p_max, i, make_float2(fmaxf(mx.x, p.x), fmaxf(mx.y, p.y)));
@@ -817,9 +892,10 @@ __device__ __forceinline__ void finish_pressure(const XArgs &a, float *line, int
                             st2(a.sen.p_min, i, make_float2(fminf(mn.x, p.x), fminf(mn.y, p.y)));
                         }
                         const size_t nrec = (size_t)a.g.nx * a.g.rows;
+                        const size_t ix = rbase + 2 * Eng::out_index(a.pi, t, m);
                         for (int h = 0; h < a.sen.n_harm; ++h) {
-                            // points i, i+1: (re, im) pairs of p e^{-i h w t}
-                            float4 *acc = reinterpret_cast<float4 *>(a.sen.harm + 2 * ((size_t)h * nrec + i));
+                            // points ix, ix+1: (re, im) pairs of p e^{-i h w t}
+                            float4 *acc = reinterpret_cast<float4 *>(a.sen.harm + 2 * ((size_t)h * nrec + ix));
                             const float c = a.sen.hw[2 * h], sn = a.sen.hw[2 * h + 1];
                             const float4 o = *acc;
                             *acc = make_float4(o.x + p.x * c, o.y - p.x * sn, o.z + p.y * c,
@@ -835,7 +911,7 @@ __device__ __forceinline__ void finish_pressure(const XArgs &a, float *line, int
         if (rec && !a.sen.all_points && a.sen.row_ptr)
             record_mask<Eng>(a, line, row, ok, t, L, b, step, v);
     }
-    row_r2c<Eng>(a, a.Sout[0] + (size_t)(ok ? row : 0) * M, ok, t, lds, v, twx, twp);
+    row_r2c<Eng>(a, a.Sout[0], b, ok, t, lds, v, twx, twp);
 }
 
 // Density update (Eqs. (4c), (8) with the split-field PML of Eq. (6)), and
@@ -890,14 +966,15 @@ __global__ void __launch_bounds__(512) kw_xden(XArgs a) {
         const int ts = t + salt;
         const RowLds ldg{sh, lds.base + salt, lds.wave};
         float2 v[E];
-        row_c2r<Eng>(a, pick3(a.Sin, g) + (size_t)rr * M, ok, ts, ldg, v, tws, tws + M, salt);
+        row_c2r<Eng>(a, pick3(a.Sin, g), b, ok, ts, ldg, v, tws, tws + M, salt);
         float *rho = pick3(a.fld, g);
         if (ok) {
 #pragma unroll
             for (int m = 0; m < E; ++m) {
                 if (m < cupd) {
                     const int x = 2 * Eng::out_index(a.pi, ts, m);
-                    const size_t i = rbase + x;
+                    const XPos i{xrow0 + 2 * (size_t)m * (Eng::out_step(a.pi) + salt),
+                                 (uint32_t)(b * nx + 2 * ts) * 4u};
                     float2 q;
                     if (g == 0) q = make_float2(a.t.pml_x[x], a.t.pml_x[x + 1]);
                     else if (g == 1) q = make_float2(qy, qy);
@@ -927,7 +1004,7 @@ __global__ void __launch_bounds__(512) kw_xden(XArgs a) {
     for (int m = 0; m < E; ++m) {
         v[m] = make_float2(0.f, 0.f);
         if (m < cupd && ok) {
-            const size_t i = rbase + 2 * Eng::out_index(a.pi, t, m);
+            const XPos i{xrow0 + 2 * (size_t)m * Eng::out_step(a.pi), xlane};
             const float2 r = sr[m];
             if constexpr (ABS) {
                 const float2 r0 = coef2_at(a.m.rho0, i);
@@ -946,8 +1023,8 @@ __global__ void __launch_bounds__(512) kw_xden(XArgs a) {
         }
     }
     if constexpr (ABS) {
-        row_r2c<Eng>(a, a.Sout[0] + (size_t)rr * M, ok, t, lds, v, tws, tws + M);
-        row_r2c<Eng>(a, a.Sout[1] + (size_t)rr * M, ok, t, lds, sr, tws, tws + M);
+        row_r2c<Eng>(a, a.Sout[0], b, ok, t, lds, v, tws, tws + M);
+        row_r2c<Eng>(a, a.Sout[1], b, ok, t, lds, sr, tws, tws + M);
     } else {
         finish_pressure<Eng>(a, line, rr, ok, t, L, b, lds, v, tws, tws + M);
     }
@@ -964,13 +1041,13 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6))) k
     float *line = reinterpret_cast<float *>(sh + (size_t)a.tb * row_pitch(M));
     float2 va[E], v[E];
     if constexpr (!MERGED)
-        row_c2r<Eng>(a, a.Sin[0] + (size_t)rr * M, ok, t, lds, va, tws, tws + M);
-    row_c2r<Eng>(a, a.Sin[MERGED ? 0 : 1] + (size_t)rr * M, ok, t, lds, v, tws, tws + M);
+        row_c2r<Eng>(a, a.Sin[0], b, ok, t, lds, va, tws, tws + M);
+    row_c2r<Eng>(a, a.Sin[MERGED ? 0 : 1], b, ok, t, lds, v, tws, tws + M);
     if (ok) {
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             if (m < cupd) {
-                const size_t i = rbase + 2 * Eng::out_index(a.pi, t, m);
+                const XPos i{xrow0 + 2 * (size_t)m * Eng::out_step(a.pi), xlane};
                 const float2 rho = ld2(a.rho_total, i);
                 const float2 c2 = coef2_at(a.m.c0sq, i);
                 float2 p;
@@ -1003,20 +1080,21 @@ __global__ void __launch_bounds__(512) kw_xfwd(XArgs a) {
     if (ok) {
 #pragma unroll
         for (int m = 0; m < E; ++m)
-            if (m < cin) v[m] = ld2(a.rsrc, rbase + 2 * Eng::in_index(a.pf, t, m));
+            if (m < cin) v[m] = ld2(a.rsrc, XPos{xrow0 + 2 * (size_t)m * Eng::in_step(a.pf), xlane});
     }
-    row_r2c<Eng>(a, a.Sout[0] + (size_t)rr * M, ok, t, lds, v, tws, tws + M);
+    row_r2c<Eng>(a, a.Sout[0], b, ok, t, lds, v, tws, tws + M);
 }
 
 template <class Eng>
 __global__ void __launch_bounds__(512) kw_xinv(XArgs a) {
     KW_XPROLOGUE
     float2 v[E];
-    row_c2r<Eng>(a, a.Sin[0] + (size_t)rr * M, ok, t, lds, v, tws, tws + M);
+    row_c2r<Eng>(a, a.Sin[0], b, ok, t, lds, v, tws, tws + M);
     if (ok) {
 #pragma unroll
         for (int m = 0; m < E; ++m)
-            if (m < cupd) st2(a.rdst, rbase + 2 * Eng::out_index(a.pi, t, m), c_scale(v[m], a.scale));
+            if (m < cupd)
+                st2(a.rdst, XPos{xrow0 + 2 * (size_t)m * Eng::out_step(a.pi), xlane}, c_scale(v[m], a.scale));
     }
 }
 
