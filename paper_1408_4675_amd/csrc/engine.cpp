@@ -663,6 +663,21 @@ int pick_tiles(kw_sim *s, int tile_y, int tile_z) {
     // rows per block in the x kernels: about 256 threads
     c.tb_x = std::max(1, 256 / c.px.L);
     while (c.tb_x > 1 && x_lds_bytes(g.M, g.nx, c.tb_x, true) > 64 * 1024) c.tb_x /= 2;
+    // rows per block of the three-group density kernel of the generic
+    // engines: as many as fit 512 threads and 64 KB of LDS
+    if (c.eng_x == ENG_G16 || c.eng_x == ENG_G32) {
+        const bool line = den_needs_line(s->med, s->src, s->sen);
+        auto fits = [&](int tb) {
+            return 3 * tb * c.px.L <= 512 && den_lds_bytes(g.M, g.nx, tb, line) <= 64 * 1024;
+        };
+        int best = 0;
+        for (int tb = 1; fits(tb); ++tb) best = tb;
+        if (best == 0)
+            return fail(KW_EUNSUPPORTED, "density pass does not fit a block (nx = %d)", g.nx);
+        c.tb_den = best;
+    } else {
+        c.tb_den = c.tb_x;
+    }
     // columns per block of the y and z passes: 16 (128-byte rows of a tile)
     // where a block can hold them -- for the fixed engines up to 1024 threads
     // and the device's LDS per block (measured at 1024^3: 120 -> 111 ms per

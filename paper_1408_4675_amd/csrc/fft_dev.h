@@ -418,6 +418,7 @@ __device__ __forceinline__ void fft_fixed(const FftPlan &P, const float2 *__rest
 template <int RM>
 struct EngGeneric {
     static constexpr int E = RM;
+    static constexpr bool fixed = false;
     __device__ static __forceinline__ int in_count(const FftPlan &P, int t) {
         const int R = plan_radix(P, 0);
         return t < P.n / R ? R : 0;
@@ -447,6 +448,7 @@ struct EngGeneric {
 template <int EE>
 struct EngFixed {
     static constexpr int E = EE;
+    static constexpr bool fixed = true;
     __device__ static __forceinline__ int in_count(const FftPlan &, int) { return EE; }
     __device__ static __forceinline__ int in_index(const FftPlan &P, int t, int m) {
         return t + m * P.L;

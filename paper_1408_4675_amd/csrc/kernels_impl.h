@@ -56,7 +56,8 @@ __device__ __forceinline__ float2 ld2(const float *p, size_t i) {
 __device__ __forceinline__ void st2(float *p, size_t i, float2 v) {
     *reinterpret_cast<float2 *>(p + i) = v;
 }
-// Element at a 32-bit byte offset from p, p uniform over the wavefront.  p
+// Element at a 32-bit byte offset from p, p uniform over the wavefront (a
+// requirement: the first active lane's p is used for all).  p
 // is read into scalar registers (readfirstlane) and accessed as global memory,
 // so that each access is one instruction with a scalar base and a vector
 // offset: no 64-bit address arithmetic per element (left to itself the
@@ -469,13 +470,28 @@ __global__ void __launch_bounds__(MAXT) kw_zfused(ZArgs a) {
     // The divergence and absorption outputs read inputs of their own: each
     // output has its own blocks (blockIdx.y = output), which keeps a block to
     // one forward and one inverse transform and its register use low.  The
-    // gradient's three outputs share one input: its block transforms the tile
-    // once and runs the three operators and inverse transforms from the kept
-    // spectrum (the pass is bound by vector ALU work, and this saves two of
-    // the six transforms of a tile).  The merged absorption (ABSM) block
-    // transforms both inputs and writes one output.
-    const int blk = blockIdx.x;
-    const int o = (MODE == ZM_GRAD) ? 0 : blockIdx.y;
+    // gradient's three outputs share one input.  With the fixed engines its
+    // block transforms the tile once and runs the three operators and
+    // inverse transforms from the kept spectrum (the pass is bound by vector
+    // ALU work, and this saves two of the six transforms of a tile).  The
+    // generic engines' register arrays are sized for their largest radix and
+    // a kept spectrum would cost them two wavefronts per SIMD, so their
+    // gradient keeps one block per output, in a 1D grid ordered so that the
+    // three blocks of a tile land on the same XCD (workgroups go round-robin
+    // over the 8 XCDs) one after another: the second and third reads of the
+    // tile hit that XCD's L2.  The merged absorption (ABSM) block transforms
+    // both inputs and writes one output.
+    constexpr bool fused_grad = MODE == ZM_GRAD && Eng::fixed;
+    int blk, o;
+    if constexpr (MODE == ZM_GRAD && !Eng::fixed) {
+        const int B = blockIdx.x, q = B >> 3;
+        blk = (q / 3) * 8 + (B & 7);
+        o = q % 3;
+        if (blk >= a.ntiles * a.g.ny) return;          // whole block: padding of the grid
+    } else {
+        blk = blockIdx.x;
+        o = (MODE == ZM_GRAD) ? 0 : blockIdx.y;
+    }
     const int f = (MODE == ZM_GRAD) ? 0 : o;
 
     ZCtx c;
@@ -510,7 +526,7 @@ __global__ void __launch_bounds__(MAXT) kw_zfused(ZArgs a) {
         stage_table(dzl, (MODE == ZM_GRAD || MODE == ZM_GRADT) ? a.t.dpz : a.t.dmz, a.g.nz);
     for (int i = threadIdx.x; i < a.g.nz; i += blockDim.x) kzl[i] = a.t.kz[i];
     __syncthreads();
-    if constexpr (MODE == ZM_GRAD) {
+    if constexpr (fused_grad) {
         Eng::template run<false>(a.pf, c.tws, t, c.lds, v);
         float2 S[E];
 #pragma unroll
@@ -580,8 +596,9 @@ struct XArgs {
 // (unnormalised; the result is nx times the inverse DFT)
 // S: the spectrum array; the row is row b of this block (rows of a block are
 // consecutive: element k of it lies at a block-uniform address plus a lane
-// offset, and M - k likewise)
-template <class Eng>
+// offset, and M - k likewise).  UB = false: S differs between the lanes of a
+// wavefront (thread groups of different fields), so plain per-lane pointers.
+template <class Eng, bool UB = true>
 __device__ __forceinline__ void row_c2r(const XArgs &a, const float2 *S, int b, bool ok,
                                         int t, const RowLds &lds, float2 (&v)[Eng::E],
                                         const float2 *twx, const float2 *twp, int salt = 0) {
@@ -595,18 +612,19 @@ __device__ __forceinline__ void row_c2r(const XArgs &a, const float2 *S, int b, 
         // k = t + m step: blk + m step + (b M + t);  M - k: blk + M - (m + 1) step + (b M + step - t)
         const uint32_t l1 = (uint32_t)(b * M + t) * 8u;
         const uint32_t l2 = (uint32_t)(b * M + step - t) * 8u;
+        const float2 *const row = S + ((size_t)blockIdx.x * a.tb + b) * M;
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             if (m < cin) {
                 const int k = Eng::in_index(a.pi, t, m);
-                const float2 P = ld_at(blk + m * step, l1);
+                const float2 P = UB ? ld_at(blk + m * step, l1) : row[k];
                 float2 xk, xm;
                 if (k == 0) {
                     xk = make_float2(P.x, 0.0f);
                     xm = make_float2(P.y, 0.0f);
                 } else {
                     xk = P;
-                    xm = ld_at(blk + M - (m + 1) * step, l2);
+                    xm = UB ? ld_at(blk + M - (m + 1) * step, l2) : row[M - k];
                 }
                 const float2 A = make_float2(xk.x + xm.x, xk.y - xm.y);        // xk + conj(xm)
                 const float2 D = make_float2(xk.x - xm.x, xk.y + xm.y);        // xk - conj(xm)
@@ -619,13 +637,14 @@ __device__ __forceinline__ void row_c2r(const XArgs &a, const float2 *S, int b, 
 }
 
 // r2c: v[m] = x[2n] + i x[2n+1], n = in_index(pf, t, m)  ->  packed spectrum row
-template <class Eng>
+template <class Eng, bool UB = true>
 __device__ __forceinline__ void row_r2c(const XArgs &a, float2 *S, int b, bool ok, int t,
                                         const RowLds &lds, float2 (&v)[Eng::E],
                                         const float2 *twx, const float2 *twp, int salt = 0) {
     constexpr int E = Eng::E;
     const int M = a.g.M;
     float2 *const blk = S + (size_t)blockIdx.x * a.tb * M;
+    float2 *const row = S + ((size_t)blockIdx.x * a.tb + b) * M;
     const int ostep = Eng::out_step(a.pf);
     const uint32_t l1 = (uint32_t)(b * M + t) * 8u;
     const float2 *tw_post = twp + salt;
@@ -651,7 +670,8 @@ __device__ __forceinline__ void row_r2c(const XArgs &a, float2 *S, int b, bool o
                     const float2 c = c_mul(tw_post[k], Bh);
                     out = make_float2(A.x + c.y, A.y - c.x);     // A - i w^k B
                 }
-                st_at(blk + m * ostep, l1, out);
+                if (UB) st_at(blk + m * ostep, l1, out);
+                else row[k] = out;
             }
         }
     }
@@ -1027,6 +1047,155 @@ __global__ void __launch_bounds__(512) kw_xden(XArgs a) {
         row_r2c<Eng>(a, a.Sout[1], b, ok, t, lds, sr, tws, tws + M);
     } else {
         finish_pressure<Eng>(a, line, rr, ok, t, L, b, lds, v, tws, tws + M);
+    }
+}
+
+// Density update for the generic engines, whose register arrays are sized for
+// their largest radix (sums of three components in registers, as kw_xden
+// keeps them, would cost two more such arrays).  The three split components are coupled only through
+// rho = sum rho_xi and sum du_xi, so a block runs them side by side: thread
+// group g (g = 0, 1, 2) transforms and updates component g of the block's tb
+// rows, and then group 0 transforms rho0 sum du and group 1 stores rho and
+// transforms it (group 2 takes the same barriers without storing).  Without
+// absorption group 1 evaluates the equation of state instead.  Each thread
+// holds one component's values, as in kw_xvel.
+// The groups exchange only what the others need: group 0 keeps du_0 and group
+// 1 keeps rho_1 in registers; rho_0, du_1 and rho_2 go to the (then idle) FFT
+// buffers of groups 0, 1 and 2, and du_2 to a line of its own.
+// LDS: [3 groups][tb rows] FFT buffers, [tb] du_2 lines (twiddles during the transforms),
+// [tb] source lines.
+// ABS (= a.m.absorbing) is a template parameter: the lossless tail (equation
+// of state, sensors, pressure transform) would otherwise set the register
+// count of the absorbing kernel too.
+template <class Eng, bool ABS>
+__global__ void __launch_bounds__(512) kw_xden3(XArgs a) {
+    constexpr int E = Eng::E;
+    extern __shared__ float2 lds_all[];
+    float2 *const sh = lds_all;
+    const int L = a.pf.L;
+    const int M = a.g.M, nx = a.g.nx, tb = a.tb;
+    const int tid = threadIdx.x;
+    const int g = tid / (tb * L);
+    const int rem = tid - g * tb * L;
+    const int b = rem / L, t = rem % L;
+    const int row = blockIdx.x * tb + b;
+    const bool ok = row < a.g.rows;
+    const int rr = ok ? row : 0;
+    const int iy = rr % a.g.ny, iz = rr / a.g.ny;
+    const size_t rbase = (size_t)rr * nx;
+    const int RP = row_pitch(M);
+    // block barriers in the transforms: the exchange below and the twiddles
+    // in the du_2 lines need every group past its transform
+    const RowLds lds{sh, (g * tb + b) * RP, false};
+    float2 *buf0 = sh + (size_t)b * RP;                      // row b's buffer of group 0
+    float2 *buf1 = sh + (size_t)(tb + b) * RP;
+    float2 *buf2 = sh + (size_t)(2 * tb + b) * RP;
+    float2 *du2 = sh + (size_t)3 * tb * RP + (size_t)b * M;   // nx floats per row
+    float *line = reinterpret_cast<float *>(sh + (size_t)3 * tb * RP + (size_t)tb * M);
+    // The twiddle tables (tw_x, and tw_post when there are two lines or more)
+    // are staged in the du_2 lines, which are free during both transforms:
+    // once for the inverse transforms of phase 1 (du_2 is written after them)
+    // and again for the forward transforms of phase 2 (after du_2 has been
+    // read).  This keeps the LDS of three 10-row blocks within a CU.
+    float2 *const tws = sh + (size_t)3 * tb * RP;
+    const bool post_lds = tb >= 2;                                    // block-uniform
+    const float2 *const twp = post_lds ? tws + M : a.t.tw_post;
+    stage_table(tws, a.t.tw_x, M);
+    if (post_lds) stage_table(tws + M, a.t.tw_post, M);
+    __syncthreads();
+    const float dt = a.g.dt;
+    const int cupd = Eng::out_count(a.pi, t);
+
+    const bool has_src = a.src.kind == KW_SOURCE_MASS &&
+                         scatter_source(a, line, rr, ok, t, L, b, g == 0);
+    const float *mysrc = line + (size_t)b * nx;
+
+    // phase 1: component g (row_c2r ends with a barrier, so the FFT buffers
+    // are free for the exchange afterwards)
+    float2 v[E];
+    row_c2r<Eng, false>(a, pick3(a.Sin, g), b, ok, t, lds, v, tws, twp);
+    {
+        float *rho = pick3(a.fld, g);
+        const float qy = a.t.pml_y[iy], qz = a.t.pml_z[iz];
+        float2 *xrho = (g == 0) ? buf0 : buf2;
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            if (m < cupd) {
+                const int n = Eng::out_index(a.pi, t, m);
+                const int x = 2 * n;
+                const size_t i = rbase + x;
+                float2 nw = make_float2(0.0f, 0.0f);
+                const float2 d = v[m];
+                if (ok) {
+                    float2 q;
+                    if (g == 0) q = make_float2(a.t.pml_x[x], a.t.pml_x[x + 1]);
+                    else if (g == 1) q = make_float2(qy, qy);
+                    else q = make_float2(qz, qz);
+                    const float2 r0 = coef2_at(a.m.rho0, i);
+                    const float2 old = ld2(rho, i);
+                    nw.x = q.x * (q.x * old.x - dt * r0.x * d.x);
+                    nw.y = q.y * (q.y * old.y - dt * r0.y * d.y);
+                    if (a.m.nonlinear) {
+                        nw.x = nw.x / (1.0f + 2.0f * dt * d.x);
+                        nw.y = nw.y / (1.0f + 2.0f * dt * d.y);
+                    }
+                    if (has_src) {
+                        nw.x += mysrc[x];
+                        nw.y += mysrc[x + 1];
+                    }
+                    st2(rho, i, nw);
+                }
+                if (g == 1) {
+                    buf1[n] = d;
+                    v[m] = nw;
+                } else {
+                    xrho[n] = nw;
+                    if (g == 2) du2[n] = d;
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // phase 2: sums over the components (group 0: sum du, group 1: rho)
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        if (m < cupd) {
+            const int n = Eng::out_index(a.pi, t, m);
+            const size_t i = rbase + 2 * n;
+            if (g == 0) {
+                if constexpr (ABS) {
+                    const float2 s = c_add(c_add(v[m], buf1[n]), du2[n]);
+                    const float2 r0 = coef2_at(a.m.rho0, i);
+                    v[m] = make_float2(r0.x * s.x, r0.y * s.y);
+                }
+            } else if (g == 1) {
+                const float2 r = c_add(c_add(v[m], buf0[n]), buf2[n]);
+                if constexpr (ABS) {
+                    v[m] = r;
+                    if (ok) st2(a.rho_total, i, r);
+                } else {
+                    const float2 c2 = coef2_at(a.m.c0sq, i);
+                    float2 pp = make_float2(c2.x * r.x, c2.y * r.y);
+                    if (a.m.nonlinear) {
+                        const float2 nl = coef2_at(a.m.nl, i);
+                        pp.x += nl.x * r.x * r.x;
+                        pp.y += nl.y * r.y * r.y;
+                    }
+                    v[m] = pp;
+                }
+            }
+        }
+    }
+    __syncthreads();   // the forward transforms below overwrite the exchanged values
+    stage_table(tws, a.t.tw_x, M);
+    if (post_lds) stage_table(tws + M, a.t.tw_post, M);
+    __syncthreads();
+    if constexpr (ABS) {
+        float2 *dst = (g == 0) ? a.Sout[0] : a.Sout[1];
+        row_r2c<Eng, false>(a, dst, b, ok && g < 2, t, lds, v, tws, twp);
+    } else {
+        finish_pressure<Eng>(a, line, rr, ok && g == 1, t, L, b, lds, v, tws, twp);
     }
 }
 

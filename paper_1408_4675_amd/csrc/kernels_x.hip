@@ -67,6 +67,22 @@ hipError_t launch_xden(hipStream_t s, const GridDev &g, const LaunchCfg &c, cons
     a.Sout[0] = Sout[0];
     a.Sout[1] = Sout[1];
     a.rho_total = rho_total;
+    if (c.eng_x == ENG_G16 || c.eng_x == ENG_G32) {
+        // generic engines: three thread groups per row (see kw_xden3)
+        a.tb = c.tb_den;
+        dim3 grid((g.rows + c.tb_den - 1) / c.tb_den);
+        dim3 block(3 * c.tb_den * c.px.L);
+        const size_t lds = den_lds_bytes(g.M, g.nx, c.tb_den, den_needs_line(m, src, sen));
+#define KW_DEN3(ENGT)                                                                              \
+    do {                                                                                           \
+        if (m.absorbing) hipLaunchKernelGGL((kw_xden3<ENGT, true>), grid, block, lds, s, a);       \
+        else hipLaunchKernelGGL((kw_xden3<ENGT, false>), grid, block, lds, s, a);                  \
+    } while (0)
+        if (c.eng_x == ENG_G16) KW_DEN3(EngGeneric<16>);
+        else KW_DEN3(EngGeneric<32>);
+#undef KW_DEN3
+        return hipGetLastError();
+    }
     dim3 grid((g.rows + c.tb_x - 1) / c.tb_x);
     dim3 block(c.tb_x * c.px.L);
     // source values and sensor lines use the FFT buffers (2 M + 2 floats a row)

@@ -70,16 +70,21 @@ hipError_t launch_zfused(hipStream_t s, const GridDev &g, const LaunchCfg &c, co
     ZArgs a = make_zargs(g, c, t, mode, in, out);
     a.sa = sa;
     a.sb = sb;
-    if ((mode == ZM_ABSM || mode == ZM_GRAD) && a.tb * c.pz.L > 512 && a.tb > 1) {
+    const bool fixed_z = c.eng_z == ENG_F8 || c.eng_z == ENG_F16;
+    if ((mode == ZM_ABSM || (mode == ZM_GRAD && fixed_z)) && a.tb * c.pz.L > 512 && a.tb > 1) {
         // the merged absorption and the gradient hold two spectra per thread:
         // they do not fit the registers of a 1024-thread block, so they run
         // half-width tiles
         a.tb /= 2;
         a.ntiles = (g.M + a.tb - 1) / a.tb;
     }
-    // one block per tile and output (the gradient's block writes all three)
-    const int nout = (mode == ZM_GRAD) ? 1 : z_outputs(mode);
-    dim3 grid(a.ntiles * g.ny, nout);
+    // one block per tile and output (with the fixed engines the gradient's
+    // block writes all three; with the generic ones its blocks come in a 1D
+    // grid in XCD-aware order, padded to whole groups of 8 tiles)
+    const int nblk = a.ntiles * g.ny;
+    dim3 grid;
+    if (mode == ZM_GRAD) grid = fixed_z ? dim3(nblk, 1) : dim3((nblk + 7) / 8 * 8 * 3, 1);
+    else grid = dim3(nblk, z_outputs(mode));
     dim3 block(a.tb * c.pz.L);
     size_t lds = zcol_lds_bytes(g.nz, a.tb);
 #define KW_ZMODES(ENGT, MAXT)                                                                  \

@@ -143,10 +143,27 @@ struct LaunchCfg {
     FftPlan py, pyi;         // y
     FftPlan pz, pzi;         // z
     int tb_x;                // rows per block in x kernels
+    int tb_den;              // rows per block of the three-group density kernel (generic engines)
     int tb_y;                // columns per block in y kernels
     int tb_z;                // columns per block in z kernels
 };
 
+// LDS of the three-group density kernel (generic engines): the FFT buffers
+// of its 3 thread groups, a line of nx floats per row for du of component z,
+// and, when `line`, one more for source values (or mask sensor values in the
+// lossless case)
+inline bool den_needs_line(const Medium &m, const SourceDev &src, const SensorDev &sen) {
+    // a mass source, or (lossless: the density kernel ends with the pressure)
+    // mask sensors or a pressure source
+    return (src.row_ptr != nullptr && src.kind == KW_SOURCE_MASS) ||
+           (!m.absorbing && ((sen.row_ptr != nullptr && !sen.all_points) ||
+                             (src.row_ptr != nullptr && src.kind == KW_SOURCE_PRESSURE)));
+}
+inline size_t den_lds_bytes(int M, int nx, int tb, bool line) {
+    const size_t rp = (size_t)M + (M >> 4) + 1;
+    return (size_t)3 * tb * rp * 8 + (size_t)tb * M * 8 +
+           (line ? (size_t)tb * nx * 4 : 0);
+}
 // LDS of the x kernels (twiddle tables, one FFT row buffer per row, and
 // optionally a line of nx floats per row), of the y pass and of the z pass
 // (twiddle table and the column tile)
