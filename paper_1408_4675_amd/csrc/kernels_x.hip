@@ -85,8 +85,9 @@ hipError_t launch_xden(hipStream_t s, const GridDev &g, const LaunchCfg &c, cons
     }
     dim3 grid((g.rows + c.tb_x - 1) / c.tb_x);
     dim3 block(c.tb_x * c.px.L);
-    // source values and sensor lines use the FFT buffers (2 M + 2 floats a row)
-    const size_t lds = x_lds(g, c, false);
+    // source values and sensor lines use the FFT buffers (2 M + 2 floats a
+    // row); the line holds the row's rho0 values of a rho0 map
+    const size_t lds = x_lds(g, c, m.rho0.map != nullptr);
     const int variant = (m.absorbing ? 1 : 0) | (src.row_ptr && src.kind == KW_SOURCE_MASS ? 2 : 0);
     switch (variant) {
     case 0: KW_ENGINE_SWITCH(c.eng_x, hipLaunchKernelGGL((kw_xden<Eng, false, false>), grid, block, lds, s, a)); break;

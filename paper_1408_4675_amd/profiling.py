@@ -56,7 +56,8 @@ def kernel_class(name: str) -> Optional[str]:
     m = re.search(r"kw_zfused<.*?>, (\d)(, \d+)?>", name)
     if m:
         return {"0": "zfused_grad", "1": "zfused_div", "2": "zfused_abs",
-                "3": "zfused_divt", "4": "zfused_gradt"}.get(m.group(1), "zfused")
+                "3": "zfused_divt", "4": "zfused_gradt",
+                "5": "zfused_abs"}.get(m.group(1), "zfused")   # 5: merged absorption
     for frag, cls in CLASS_OF:
         if cls and frag in name:
             return cls
