@@ -107,6 +107,12 @@ def candidates(axis: int, n: int) -> List[Tuple[List[int], int]]:
         scheds = [s for s in scheds if len(s) <= mn + 1]
         if n >= 64:
             scheds += [s for s in _factorisations(n, (32, 16, 8), 2) if 32 in s]
+        # the four-wide fixed engine (radices up to 4: more passes, fewer
+        # registers per thread)
+        four = _factorisations(n, (4, 2), 8)
+        if four:
+            mn4 = min(len(s) for s in four)
+            scheds += [s for s in four if len(s) == mn4 and s not in scheds][:1]
     else:
         scheds = _factorisations(n, (16, 15, 12, 10, 8, 6, 5, 4, 3, 2), 3)
         mn = min(len(s) for s in scheds)

@@ -169,7 +169,8 @@ bool axis_plan(int n, int axis, const std::vector<int> *rad, int &eng, FftPlan &
         if (rad) {
             r = *rad;
             // the width is the largest radix of a caller-chosen schedule
-            E = *std::max_element(r.begin(), r.end()) > 8 ? 16 : 8;
+            const int rm = *std::max_element(r.begin(), r.end());
+            E = rm > 8 ? 16 : rm > 4 ? 8 : 4;
         } else {
             int m = n;
             while (m > 1) {
@@ -180,7 +181,7 @@ bool axis_plan(int n, int axis, const std::vector<int> *rad, int &eng, FftPlan &
             }
         }
         if (fixed_plan_from_radices(n, E, r, f)) {
-            eng = E == 16 ? ENG_F16 : ENG_F8;
+            eng = E == 16 ? ENG_F16 : E == 8 ? ENG_F8 : ENG_F4;
             i = f;
             return true;
         }

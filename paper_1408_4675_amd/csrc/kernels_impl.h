@@ -1288,6 +1288,7 @@ __global__ void __launch_bounds__(512) kw_xinv(XArgs a) {
     switch (ENG) {                                                             \
     case ENG_G16: { using Eng = EngGeneric<16>; BODY; } break;                 \
     case ENG_G32: { using Eng = EngGeneric<32>; BODY; } break;                 \
+    case ENG_F4:  { using Eng = EngFixed<4>; BODY; } break;                    \
     case ENG_F8:  { using Eng = EngFixed<8>; BODY; } break;                    \
     default:      { using Eng = EngFixed<16>; BODY; } break;                   \
     }

@@ -70,7 +70,7 @@ hipError_t launch_zfused(hipStream_t s, const GridDev &g, const LaunchCfg &c, co
     ZArgs a = make_zargs(g, c, t, mode, in, out);
     a.sa = sa;
     a.sb = sb;
-    const bool fixed_z = c.eng_z == ENG_F8 || c.eng_z == ENG_F16;
+    const bool fixed_z = eng_fixed(c.eng_z);
     if ((mode == ZM_ABSM || (mode == ZM_GRAD && fixed_z)) && a.tb * c.pz.L > 512 && a.tb > 1) {
         // the merged absorption and the gradient hold two spectra per thread:
         // they do not fit the registers of a 1024-thread block, so they run

@@ -30,10 +30,12 @@ def _banner(name):
     print("\n[case] %s" % name, flush=True)
 
 
-def _run_both(kw, scen, steps, graph_steps=None):
+def _run_both(kw, scen, steps, graph_steps=None, plans=()):
     A, Simulation = kw
-    _banner("%s steps=%d" % (scen.name, steps))
+    _banner("%s steps=%d plans %s" % (scen.name, steps, list(plans)))
     sim = Simulation(scen, graph_steps=graph_steps)
+    for axis, rad in plans:
+        sim.set_plan(axis, rad)
     sim.step(steps)
     orc = Oracle(scen)
     orc.step(steps)
@@ -270,7 +272,8 @@ def test_fft_engines_and_schedules_agree(kw):
     p_ref = ref.gather(A.KW_REC_P_FINAL, device=False)
     for plans in ([(0, [8, 4]), (1, [8, 4]), (2, [8, 8])],
                   [(0, [32]), (1, [32]), (2, [32, 2])],
-                  [(0, [2, 16]), (1, [4, 8]), (2, [4, 16])]):
+                  [(0, [2, 16]), (1, [4, 8]), (2, [4, 16])],
+                  [(0, [4, 4, 2]), (1, [4, 4, 2]), (2, [4, 4, 4])]):
         sim = Simulation(scen)
         for axis, rad in plans:
             sim.set_plan(axis, rad)
@@ -278,6 +281,25 @@ def test_fft_engines_and_schedules_agree(kw):
         e = rel_l2(sim.gather(A.KW_REC_P_FINAL, device=False), p_ref)
         print("  plans %s rel %.2e" % (plans, e))
         assert e < 1e-5
+
+
+FOUR = [((32, 16, 64), [(0, [4, 4]), (1, [4, 4]), (2, [4, 4, 4])]),
+        ((256, 12, 10), [(0, [4, 4, 4, 2])]),
+        ((64, 20, 30), [(0, [4, 2, 4])])]
+
+
+@pytest.mark.parametrize("shape,plans", FOUR, ids=["%dx%dx%d" % f[0] for f in FOUR])
+def test_parity_four_wide_engine(kw, shape, plans):
+    """The four-wide fixed engine (radices up to 4, 32 threads a 128-point
+    row) on every pass kind, heterogeneous nonlinear absorbing medium with a
+    mass source and a PML, against the oracle."""
+    nx, ny, nz = shape
+    scen = sc.small_case(nx, ny, nz, seed=5, heterogeneous=True, nonlinear=True, absorbing=True,
+                         pml=3, steps=8, sensor_mask=False)
+    sim, orc = _run_both(kw, scen, 8, plans=plans)
+    errs, tol = compare_outputs(sim, orc, scen, REPORT)
+    for k, e in errs.items():
+        assert e <= tol, (k, e)
 
 
 # 1024-point y and z columns run in 1024-thread blocks of 16 columns; (40, 6,
