@@ -32,16 +32,17 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def measured_traffic(kernel_class, launches_bytes):
+def measured_traffic(kernel_class, npts):
     """HBM bytes per launch of `kernel_class` from the committed rocprofv3 PMC
-    summary, if it was taken on the current kernel sources; else None."""
+    summary, if it was taken on the current kernel sources and on a grid of
+    `npts` points (the workload being reported); else None."""
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         d = json.load(fh)
     from paper_1408_4675_amd.profiling import kernel_source_hash
-    if d.get("source_hash") != kernel_source_hash():
+    if d.get("source_hash") != kernel_source_hash() or d.get("points") != npts:
         return None
     k = d.get("kernels", {}).get(kernel_class)
     return None if k is None else k.get("hbm_bytes_per_launch")
@@ -98,7 +99,7 @@ def roofline(stats, npts):
                  for k, v in classes.items()}
     return dom, dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                      frac=round(achieved / HBM_PEAK_GBS, 4),
-                     traffic=measured_traffic(dom, c["bytes"]),
+                     traffic=measured_traffic(dom, npts),
                      kernel=dom, algorithmic_bytes_per_launch=c["bytes"],
                      avg_launch_ms=round(avg_s * 1e3, 5)), per_class
 

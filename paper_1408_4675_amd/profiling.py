@@ -8,7 +8,7 @@ calibrates the HBM traffic counters.
         turn the kernel_stats.csv that `rocprofv3 --kernel-trace --stats
         --output-format csv` wrote under DIR into a short Markdown table
     python -m paper_1408_4675_amd.profiling traffic --fetch DIR --write DIR
-            --copy-fetch DIR --copy-write DIR --copy-mib N --out FILE.json --command C
+            --copy-fetch DIR --copy-write DIR --copy-mib N --points P --out FILE.json --command C
         mean FETCH_SIZE and WRITE_SIZE per dispatch of every kernel class,
         scaled by what the counters read for the copy kernel, as JSON with the
         hash of the kernel sources they were taken on
@@ -194,6 +194,8 @@ def main(argv=None):
     for k in ("fetch", "write", "copy-fetch", "copy-write", "out", "command"):
         p.add_argument("--" + k, required=True)
     p.add_argument("--copy-mib", type=float, default=1024)
+    p.add_argument("--points", type=int, required=True,
+                   help="grid points of the profiled workload (the table applies to that grid only)")
     a = ap.parse_args(argv)
     if a.cmd == "copy":
         copy_probe(a.mib, a.reps)
@@ -204,6 +206,7 @@ def main(argv=None):
     else:
         d = traffic_table(a.fetch, a.write, a.copy_fetch, a.copy_write, a.copy_mib)
         d["command"] = a.command
+        d["points"] = a.points
         with open(a.out, "w") as fh:
             json.dump(d, fh, indent=1, sort_keys=True)
         print(json.dumps(d["kernels"], indent=1))
