@@ -363,8 +363,9 @@ def main():
         try:
             log("building 1024^3 water workload")
             big = sc.water_bowl_large(n=1024, steps=args.large_steps)
-            log("timing 1024^3: %d steps after 5 warm-up" % args.large_steps)
-            bsecs, bpsecs, bstats = time_workload(big, args.large_steps, 5)
+            warm = min(20, args.large_steps)
+            log("timing 1024^3: %d steps after %d warm-up" % (args.large_steps, warm))
+            bsecs, bpsecs, bstats = time_workload(big, args.large_steps, warm)
             bms = bsecs / args.large_steps * 1e3
             bdom, broof, bper = roofline(bstats, big.grid.npts)
             bstep = pass_model_bytes(bstats) / args.large_steps
