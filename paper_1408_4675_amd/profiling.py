@@ -4,9 +4,10 @@ calibrates the HBM traffic counters.
     python -m paper_1408_4675_amd.profiling copy [--mib N] [--reps K]
         a device-to-device copy of N MiB, K times (the reference kernel whose
         FETCH_SIZE / WRITE_SIZE give bytes-per-KiB scale factors)
-    python -m paper_1408_4675_amd.profiling stats DIR --out FILE.md --title T --command C
+    python -m paper_1408_4675_amd.profiling stats DIR --out FILE.md --title T --command C [--min-us U]
         turn the kernel_stats.csv that `rocprofv3 --kernel-trace --stats
-        --output-format csv` wrote under DIR into a short Markdown table
+        --output-format csv` wrote under DIR into a short Markdown table (with
+        --min-us, from kernel_trace.csv, dispatches of at least U us only)
     python -m paper_1408_4675_amd.profiling traffic --fetch DIR --write DIR
             --copy-fetch DIR --copy-write DIR --copy-mib N --points P --out FILE.json --command C
         mean FETCH_SIZE and WRITE_SIZE per dispatch of every kernel class,
@@ -94,11 +95,34 @@ def read_kernel_stats(d: str) -> List[Dict]:
     return out
 
 
-def stats_markdown(d: str, title: str, command: str) -> str:
-    rows = read_kernel_stats(d)
+def read_kernel_trace(d: str, min_us: float) -> List[Dict]:
+    """Per kernel name, calls and durations of the dispatches in
+    kernel_trace.csv that lasted at least `min_us` microseconds."""
+    with open(_find(d, "kernel_trace.csv")) as fh:
+        rows = list(csv.DictReader(fh))
+    per: Dict[str, List[float]] = {}
+    for r in rows:
+        ns = float(_col(r, "End_Timestamp")) - float(_col(r, "Start_Timestamp"))
+        if ns >= min_us * 1e3:
+            per.setdefault(_col(r, "Kernel_Name"), []).append(ns)
+    tot = sum(sum(v) for v in per.values()) or 1.0
+    out = [dict(name=k, calls=len(v), total_ns=sum(v), avg_ns=sum(v) / len(v),
+                pct=100.0 * sum(v) / tot) for k, v in per.items()]
+    out.sort(key=lambda r: -r["total_ns"])
+    return out
+
+
+def stats_markdown(d: str, title: str, command: str, min_us: float = 0.0) -> str:
+    if min_us > 0:
+        rows = read_kernel_trace(d, min_us)
+        source = ("rocprofv3 kernel_trace.csv, dispatches of at least %g us only (this "
+                  "selects the large workload's launches)" % min_us)
+    else:
+        rows = read_kernel_stats(d)
+        source = "rocprofv3 kernel_stats.csv"
     lines = ["# %s" % title, "", "Command (from the repository root, on one MI355X; "
              "R is the repository root):", "", "    " + command, "",
-             "Durations in microseconds, from rocprofv3 kernel_stats.csv.", "",
+             "Durations in microseconds, from %s." % source, "",
              "| kernel | class | calls | total us | average us | % |", "|---|---|---|---|---|---|"]
     for r in rows:
         lines.append("| %s | %s | %d | %.1f | %.2f | %.1f |" % (
@@ -190,6 +214,8 @@ def main(argv=None):
     p.add_argument("--out", required=True)
     p.add_argument("--title", required=True)
     p.add_argument("--command", required=True)
+    p.add_argument("--min-us", type=float, default=0.0,
+                   help="summarise only dispatches at least this long (from kernel_trace.csv)")
     p = sub.add_parser("traffic")
     for k in ("fetch", "write", "copy-fetch", "copy-write", "out", "command"):
         p.add_argument("--" + k, required=True)
@@ -201,7 +227,7 @@ def main(argv=None):
         copy_probe(a.mib, a.reps)
     elif a.cmd == "stats":
         with open(a.out, "w") as fh:
-            fh.write(stats_markdown(a.dir, a.title, a.command))
+            fh.write(stats_markdown(a.dir, a.title, a.command, a.min_us))
         print("wrote", a.out)
     else:
         d = traffic_table(a.fetch, a.write, a.copy_fetch, a.copy_write, a.copy_mib)
