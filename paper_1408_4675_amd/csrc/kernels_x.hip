@@ -89,12 +89,20 @@ hipError_t launch_xden(hipStream_t s, const GridDev &g, const LaunchCfg &c, cons
     // row); the line holds the row's rho0 values of a rho0 map
     const size_t lds = x_lds(g, c, m.rho0.map != nullptr);
     const int variant = (m.absorbing ? 1 : 0) | (src.row_ptr && src.kind == KW_SOURCE_MASS ? 2 : 0);
-    switch (variant) {
-    case 0: KW_ENGINE_SWITCH(c.eng_x, hipLaunchKernelGGL((kw_xden<Eng, false, false>), grid, block, lds, s, a)); break;
-    case 1: KW_ENGINE_SWITCH(c.eng_x, hipLaunchKernelGGL((kw_xden<Eng, true, false>), grid, block, lds, s, a)); break;
-    case 2: KW_ENGINE_SWITCH(c.eng_x, hipLaunchKernelGGL((kw_xden<Eng, false, true>), grid, block, lds, s, a)); break;
-    default: KW_ENGINE_SWITCH(c.eng_x, hipLaunchKernelGGL((kw_xden<Eng, true, true>), grid, block, lds, s, a)); break;
-    }
+    // fixed engines only (the generic ones took the branch above)
+#define KW_DEN1(ENGT)                                                                              \
+    do {                                                                                           \
+        switch (variant) {                                                                         \
+        case 0: hipLaunchKernelGGL((kw_xden<ENGT, false, false>), grid, block, lds, s, a); break;  \
+        case 1: hipLaunchKernelGGL((kw_xden<ENGT, true, false>), grid, block, lds, s, a); break;   \
+        case 2: hipLaunchKernelGGL((kw_xden<ENGT, false, true>), grid, block, lds, s, a); break;   \
+        default: hipLaunchKernelGGL((kw_xden<ENGT, true, true>), grid, block, lds, s, a); break;   \
+        }                                                                                          \
+    } while (0)
+    if (c.eng_x == ENG_F4) KW_DEN1(EngFixed<4>);
+    else if (c.eng_x == ENG_F8) KW_DEN1(EngFixed<8>);
+    else KW_DEN1(EngFixed<16>);
+#undef KW_DEN1
     return hipGetLastError();
 }
 
