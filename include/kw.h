@@ -214,10 +214,14 @@ int kw_stats(kw_sim *sim, kw_stats_t *out);
  * the default is 8). */
 int kw_set_graph(kw_sim *sim, int32_t steps_per_graph);
 
-/* Override the FFT radix schedule of one axis (0 = x, 1 = y, 2 = z) and the
- * column-tile width of the y/z passes.  radices lists the factors of the
- * transform length in forward order (product must equal the length: nx/2 for
- * x).  Used by the autotuner; must be called before the first kw_step. */
+/* Override the FFT radix schedule of one axis (0 = x, 1 = y, 2 = z) and its
+ * tile: columns per block of the y/z passes, rows per block of the x passes
+ * (0 = the default).  radices lists the factors of the transform length in
+ * forward order (product must equal the length: nx/2 for x).  For a
+ * power-of-two length, radices of at most 4, 8 or 16 (each a power of two)
+ * run on the 4-, 8- or 16-wide fixed engine; other schedules on the generic
+ * one.  Used by the autotuner; must be called before the first kw_step.
+ * Returns KW_EUNSUPPORTED for a schedule or tile no engine can run. */
 int kw_set_plan(kw_sim *sim, int axis, const int32_t *radices, int32_t n_radices,
                 int32_t tile);
 
