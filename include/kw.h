@@ -221,7 +221,9 @@ int kw_set_graph(kw_sim *sim, int32_t steps_per_graph);
  * power-of-two length, radices of at most 4, 8 or 16 (each a power of two)
  * run on the 4-, 8- or 16-wide fixed engine; other schedules on the generic
  * one.  Used by the autotuner; must be called before the first kw_step.
- * Returns KW_EUNSUPPORTED for a schedule or tile no engine can run. */
+ * Returns KW_EINVAL for radices that do not form a schedule of the length,
+ * KW_EUNSUPPORTED for a tile that does not fit a block (the plan is then
+ * left as it was), KW_ESTATE after the first step. */
 int kw_set_plan(kw_sim *sim, int axis, const int32_t *radices, int32_t n_radices,
                 int32_t tile);
 
