@@ -7,7 +7,10 @@ resident in its own workspace and runs on its own stream, advanced in chunks of
 `chunk_steps` steps (captured HIP graphs); a chunk is enqueued as soon as the
 previous one of that simulation has finished, so simulations of different
 sizes interleave on the GPU (continuous batching).  Set-up (host tables and the
-upload) runs in a worker thread so that it overlaps the GPU work of the others.
+upload) runs in the scheduling thread, between chunks: the GPU keeps working
+on the chunks already enqueued meanwhile.  (Set-up in worker threads, with
+HIP calls from several host threads at once, was switched off after a heap
+corruption abort in such a run whose cause was not found.)
 Each result is computed by exactly the same kernels, in the same order, as
 when the request runs alone, so it is bit-for-bit the same.
 
@@ -18,7 +21,6 @@ schedules.
 """
 from __future__ import annotations
 
-import concurrent.futures as cf
 import time
 from dataclasses import dataclass, field
 from typing import Callable, Dict, List, Optional, Sequence
@@ -69,8 +71,7 @@ class Server:
     """Continuous-batching scheduler over one GPU."""
 
     def __init__(self, budget_bytes: Optional[int] = None, max_active: int = 8,
-                 chunk_steps: int = 64, keep_outputs: bool = False, setup_workers: int = 2,
-                 device: str = "cuda"):
+                 chunk_steps: int = 64, keep_outputs: bool = False, device: str = "cuda"):
         self.device = torch.device(device)
         if budget_bytes is None:
             free, _ = torch.cuda.mem_get_info(self.device)
@@ -79,7 +80,6 @@ class Server:
         self.max_active = max_active
         self.chunk = chunk_steps
         self.keep = keep_outputs
-        self.workers = setup_workers
         self.peak_used = 0             # largest sum of admitted footprints seen
         self.peak_active = 0           # largest number of simulations admitted at once
 
@@ -92,27 +92,22 @@ class Server:
                 raise ValueError("request %d needs %d bytes, budget is %d"
                                  % (r.rid, foot[r.rid], self.budget))
         pending = list(reqs)
-        setting_up: Dict[int, cf.Future] = {}
         active: List[_Active] = []
         results: List[Result] = []
         used = 0
-        pool = cf.ThreadPoolExecutor(max_workers=self.workers)
         t0 = time.perf_counter()
         try:
-            while pending or setting_up or active:
+            while pending or active:
                 now = time.perf_counter() - t0
                 # admission: arrived, a slot free, footprint within budget (in order)
                 while (pending and pending[0].arrival <= now
-                       and len(active) + len(setting_up) < self.max_active
+                       and len(active) < self.max_active
                        and used + foot[pending[0].rid] <= self.budget):
                     r = pending.pop(0)
                     used += foot[r.rid]
-                    setting_up[r.rid] = pool.submit(self._create, r, now)
+                    active.append(self._create(r, now))
                     self.peak_used = max(self.peak_used, used)
-                    self.peak_active = max(self.peak_active, len(active) + len(setting_up))
-                # set-ups that finished join the active set
-                for rid in [k for k, f in setting_up.items() if f.done()]:
-                    active.append(setting_up.pop(rid).result())
+                    self.peak_active = max(self.peak_active, len(active))
                 progressed = False
                 for a in list(active):
                     if a.event is not None and not a.event.query():
@@ -140,7 +135,6 @@ class Server:
                     nxt = pending[0].arrival - (time.perf_counter() - t0) if pending else 1.0
                     time.sleep(max(0.0, min(nxt, 2e-4)))
         finally:
-            pool.shutdown(wait=True)
             for a in active:
                 a.sim.close()
         return sorted(results, key=lambda r: r.rid)
