@@ -61,3 +61,56 @@ def test_mixed_results_equal_alone_and_budget_holds():
         assert set(r.outputs) == set(a.outputs) and r.outputs
         for k in r.outputs:
             assert np.array_equal(r.outputs[k], a.outputs[k]), (r.rid, k)
+
+
+def test_scheduler_admission_budget_and_chunks(monkeypatch):
+    """The scheduler alone, on a stand-in for the simulation (no GPU): requests
+    are admitted in arrival order within the footprint budget and the slot
+    limit, every request runs exactly its steps in chunks, and each finishes."""
+    import paper_1408_4675_amd.serving as S
+
+    log = {"active": 0, "peak": 0, "steps": {}, "order": []}
+
+    class FakeSim:
+        def __init__(self, scen, device="cuda"):
+            self.scen = scen
+            self.stream = None
+            log["active"] += 1
+            log["peak"] = max(log["peak"], log["active"])
+            log["order"].append(scen.name)
+
+        def step(self, n):
+            log["steps"][self.scen.name] = log["steps"].get(self.scen.name, 0) + n
+
+        def gather(self, what, device=False):
+            return np.zeros(1, np.float32)
+
+        def close(self):
+            log["active"] -= 1
+
+    class FakeEvent:
+        def record(self, stream):
+            pass
+
+        def query(self):
+            return True
+
+    reqs = sc.serving_trace(seed=2, n_requests=12, rate=1e6, sizes=(32, 48), medium_pool=1,
+                            steps_range=(5, 40))
+    for i, r in enumerate(reqs):
+        r.scenario.name = "r%d" % i
+    foot = {id(r.scenario): (100 if r.scenario.grid.nx == 32 else 250) for r in reqs}
+    monkeypatch.setattr(S, "Simulation", FakeSim)
+    monkeypatch.setattr(S, "workspace_size", lambda scen: foot[id(scen)])
+    monkeypatch.setattr(S.torch.cuda, "Event", FakeEvent)
+    monkeypatch.setattr(S.A, "load", lambda *a, **k: None)
+    srv = S.Server(budget_bytes=600, max_active=3, chunk_steps=16)
+    res = srv.run(reqs)
+    assert len(res) == 12 and log["active"] == 0
+    assert log["order"] == ["r%d" % i for i in range(12)]          # arrival order
+    assert srv.peak_active <= 3 and log["peak"] <= 3
+    assert srv.peak_used <= 600
+    for i, r in enumerate(reqs):
+        assert log["steps"]["r%d" % i] == r.scenario.steps
+    with pytest.raises(ValueError):
+        S.Server(budget_bytes=50, max_active=3).run(reqs)            # a request above budget
