@@ -36,6 +36,11 @@ is also listed in the design notes):
   * Absorption coefficient: alpha0 [Np (rad/s)^-y m^-1]
         = 100 alpha0[dB/(MHz^y cm)] / (20 log10 e) / (2 pi 1e6)^y.
   * Sensors record p^(n+1) after every step whose number n+1 >= record_start.
+
+Parity unpinned (no closed form or invariant fixes these readings; they are
+checked only as GPU = oracle): the PML profile constants, the interpolation
+of rho0 to the staggered points, the bowl voxelisation and the source time
+sampling.
 """
 from __future__ import annotations
 

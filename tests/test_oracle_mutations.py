@@ -61,6 +61,57 @@ def _transposed_axes(o):           # x and y wavenumbers exchanged on a non-cubi
     o.d_plus = [o.d_plus[1], o.d_plus[0], o.d_plus[2]]
 
 
+def _override(**members):
+    """Mutant that replaces methods or properties of the class of `o`."""
+    def mutate(o):
+        o.__class__ = type("Mutant", (type(o),), members)
+    return mutate
+
+
+def _rms_no_sqrt_fn(self):
+    return self.p_sum2 / max(self.n_rec, 1)
+
+
+def _rms_extra_count_fn(self):
+    return np.sqrt(self.p_sum2 / (self.n_rec + 1))
+
+
+def _intensity_c0_squared_fn(self):
+    rc = (self.rho0 * self.c0 ** 2).reshape(-1)
+    if self.sensor_index is not None:
+        rc = rc[self.sensor_index]
+    return self.p_sum2 / max(self.n_rec, 1) / rc
+
+
+def _record_one_step_early(self):
+    # the window opens one step before record_start
+    self.record_start -= 1
+    ok.Oracle._record(self)
+    self.record_start += 1
+
+
+def _record_peak_magnitude(self):
+    # |p| where the peak positive pressure belongs
+    before = self.p_max.copy()
+    ok.Oracle._record(self)
+    if self.n >= self.record_start:
+        flat = self.p.reshape(-1)
+        v = flat if self.sensor_index is None else flat[self.sensor_index]
+        self.p_max = np.maximum(before, np.abs(v))
+
+
+_rms_no_sqrt = _override(p_rms=property(_rms_no_sqrt_fn))
+_rms_no_sqrt.__name__ = "_rms_no_sqrt"
+_rms_extra_count = _override(p_rms=property(_rms_extra_count_fn))
+_rms_extra_count.__name__ = "_rms_extra_count"
+_intensity_c0_squared = _override(intensity=_intensity_c0_squared_fn)
+_intensity_c0_squared.__name__ = "_intensity_c0_squared"
+_window_early = _override(_record=_record_one_step_early)
+_window_early.__name__ = "_window_early"
+_peak_magnitude = _override(_record=_record_peak_magnitude)
+_peak_magnitude.__name__ = "_peak_magnitude"
+
+
 MUTANTS = [
     (_normalised_sinc, [lambda: pins.test_green_function_exact((12, 10, 16), 400)]),
     (_no_kappa, [lambda: pins.test_oblique_plane_wave_exact()]),
@@ -72,6 +123,11 @@ MUTANTS = [
     (_eta_dropped, [lambda: pins.test_absorption_rate_and_dispersion_match_power_law(1.5)]),
     (_source_scale, [lambda: pins.test_plane_source_emits_its_drive_amplitude()]),
     (_transposed_axes, [lambda: pins.test_gradient_is_exact_shifted_derivative((1, 2, 3))]),
+    (_rms_no_sqrt, [lambda: pins.test_aggregates_of_exact_plane_wave(False)]),
+    (_rms_extra_count, [lambda: pins.test_aggregates_of_exact_plane_wave(False)]),
+    (_intensity_c0_squared, [lambda: pins.test_aggregates_of_exact_plane_wave(True)]),
+    (_window_early, [lambda: pins.test_aggregates_follow_exact_green_function_series()]),
+    (_peak_magnitude, [lambda: pins.test_aggregates_follow_exact_green_function_series()]),
 ]
 
 

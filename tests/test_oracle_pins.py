@@ -609,3 +609,83 @@ def test_pressure_source_imposes_values_and_is_linear():
     o2.step(scen.steps)
     assert np.max(np.abs(o2.p - 2 * o.p)) <= 1e-12 * np.max(np.abs(o2.p))
     assert np.max(np.abs(o2.u[0] - 2 * o.u[0])) <= 1e-12 * np.max(np.abs(o2.u[0]))
+
+
+# ---------------------------------------------------------------------------
+# aggregate outputs kept in memory (peak pressure, rms pressure, intensity),
+# pinned by solutions whose time series is known in closed form
+# ---------------------------------------------------------------------------
+
+def _plane_wave_aggregates(sensor_index=None):
+    """Exact oblique plane wave p = A cos(k.x - w t) on a periodic lossless
+    grid, sampled 40 times per period and recorded over the last two whole
+    periods."""
+    n, dx, c0, rho0, A = 16, 1e-4, 1500.0, 1000.0, 1e5
+    kvec = 2 * np.pi * np.array([2, 1, 1]) / (n * dx)
+    k = np.linalg.norm(kvec)
+    w = c0 * k
+    per_period = 40
+    dt = 2 * np.pi / w / per_period
+    g = sc.Grid(n, n, n, dx, dx, dx, dt=dt, cfl=0.0, pml_size=(0, 0, 0))
+    med = sc.Medium(c0, rho0, 0.0, 5.0, 1.5, nonlinear=False, absorbing=False)
+    steps = 3 * per_period
+    sen = sc.Sensor(record=sc.REC_P_MAX | sc.REC_P_RMS | sc.REC_INTENSITY, index=sensor_index,
+                    record_start=steps - 2 * per_period + 1)
+    o = Oracle(sc.Scenario("plane_agg", g, med, None, sen, steps))
+    z, y, x = np.meshgrid(np.arange(n) * dx, np.arange(n) * dx, np.arange(n) * dx, indexing="ij")
+    phase = kvec[0] * x + kvec[1] * y + kvec[2] * z
+    o.set_pressure(A * np.cos(phase))
+    for a in range(3):
+        o.u[a] = A * kvec[a] / (rho0 * c0 * k) * np.cos(phase + kvec[a] * dx / 2 + w * dt / 2)
+    o.step(steps)
+    return o, A, rho0, c0, per_period
+
+
+@pytest.mark.parametrize("mask", [False, True])
+def test_aggregates_of_exact_plane_wave(mask):
+    """Over whole periods of p = A cos(w t - k.x) sampled N times per period
+    (N > 2), the mean of p^2 is A^2/2 exactly: p_rms = A/sqrt(2) and the
+    intensity p^2/(rho0 c0) averages to A^2/(2 rho0 c0) at every point; the
+    running maximum lies between A cos(pi/N) and A (the sampled peak)."""
+    idx = np.array([0, 17, 300, 1234, 4095], np.int64) if mask else None
+    o, A, rho0, c0, N = _plane_wave_aggregates(idx)
+    npts = 16 ** 3 if idx is None else idx.size
+    assert o.n_rec == 2 * N
+    assert o.p_rms.shape == (npts,)
+    assert np.max(np.abs(o.p_rms - A / np.sqrt(2.0))) < 1e-9 * A
+    I = o.intensity()
+    assert I.shape == (npts,)
+    assert np.max(np.abs(I - A * A / (2 * rho0 * c0))) < 1e-9 * A * A / (rho0 * c0)
+    assert np.all(o.p_max >= A * np.cos(np.pi / N) * (1 - 1e-9))
+    assert np.all(o.p_max <= A * (1 + 1e-9))
+
+
+def test_aggregates_follow_exact_green_function_series():
+    """Lossless homogeneous periodic grid started on the Green's function
+    initial state: p^n = IFT(cos(c0 k n dt) FT p0) exactly for every n.  The
+    recorded aggregates equal the maximum, root mean square and mean of
+    p^2 / (rho0 c0) of that closed-form series over steps record_start..n
+    (a non-periodic series, so the window's first and last step matter)."""
+    nx, ny, nz = 10, 9, 12
+    c0, rho0 = 1500.0, 1000.0
+    steps, start = 23, 6
+    idx = np.array([3, 77, 500, 801, nx * ny * nz - 1], np.int64)
+    for index in (None, idx):
+        sen = sc.Sensor(record=sc.REC_P_MAX | sc.REC_P_RMS | sc.REC_INTENSITY, index=index,
+                        record_start=start)
+        o = Oracle(_case(nx, ny, nz, dx=1e-4, dy=1.2e-4, dz=0.9e-4, cfl=0.4, sensor=sen))
+        rng = np.random.default_rng(21)
+        p0 = rng.standard_normal(o.shape)
+        _green_init(o, p0)
+        o.step(steps)
+        P0 = np.fft.fftn(p0)
+        series = np.array([np.fft.ifftn(np.cos(c0 * o.k * m * o.dt) * P0).real.reshape(-1)
+                           for m in range(start, steps + 1)])
+        if index is not None:
+            series = series[:, index]
+        scale = np.max(np.abs(series))
+        assert o.n_rec == steps - start + 1
+        assert np.max(np.abs(o.p_max - series.max(axis=0))) < 1e-11 * scale
+        assert np.max(np.abs(o.p_rms - np.sqrt(np.mean(series ** 2, axis=0)))) < 1e-11 * scale
+        assert np.max(np.abs(o.intensity() - np.mean(series ** 2, axis=0) / (rho0 * c0))) \
+            < 1e-11 * scale * scale / (rho0 * c0)
