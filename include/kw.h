@@ -26,8 +26,13 @@
  *     (a hipStream_t passed as void*; NULL is the default stream).
  *   - Every function returns a status code; on failure kw_last_error() gives a
  *     thread-local message.  Nothing aborts and no exception crosses the ABI.
- *   - One thread may use a simulation at a time.  Simulations on different
- *     streams may run concurrently.
+ *   - Threads: kw_prepare, kw_plan_workspace_size and kw_plan_destroy make no
+ *     HIP call and may run in any number of host threads at once.  Every
+ *     other call may use the device; make all of them from one host thread.
+ *     Several simulations may be driven from that thread, each on a stream of
+ *     its own, and their work then overlaps on the GPU.  Simulations that share
+ *     a stream are serialised on it.  Device calls from several host threads
+ *     at once are not supported.
  */
 #ifndef KW_H
 #define KW_H
@@ -182,6 +187,31 @@ int kw_create(const kw_grid *grid, const kw_medium *medium, const kw_source *sou
               const kw_sensor *sensor, void *dev_workspace, size_t ws_bytes,
               void *stream, kw_sim **out);
 
+/* Set-up in two parts, for callers that prepare simulations off the thread
+ * that drives the GPU (a serving loop):
+ *   kw_prepare       everything kw_create does on the host -- validation, FFT
+ *                    plans, the 1D operator tables of Eqs. (4a), (4c), (5), (8)
+ *                    and the per-point medium coefficients in float64, source
+ *                    and sensor lists -- and no HIP call.  The host arrays of
+ *                    the inputs are copied; *out owns host memory only.  Same
+ *                    status codes as kw_create for invalid inputs.
+ *   kw_plan_workspace_size  device bytes kw_create_prepared needs (equal to
+ *                    kw_workspace_size of the same inputs); 0 for NULL.
+ *   kw_create_prepared  the device part of kw_create: binds a workspace and a
+ *                    stream, uploads and zeroes the state (KW_EINVAL for a NULL
+ *                    or misaligned workspace, KW_ENOMEM when it is too small,
+ *                    KW_EDEVICE for a HIP error).  The plan is only read: it may
+ *                    be destroyed afterwards or used for more simulations.
+ *   kw_plan_destroy  frees the plan; NULL-safe.
+ * kw_create is kw_prepare followed by kw_create_prepared. */
+typedef struct kw_plan kw_plan;
+int kw_prepare(const kw_grid *grid, const kw_medium *medium, const kw_source *source,
+               const kw_sensor *sensor, kw_plan **out);
+size_t kw_plan_workspace_size(const kw_plan *plan);
+int kw_create_prepared(const kw_plan *plan, void *dev_workspace, size_t ws_bytes, void *stream,
+                       kw_sim **out);
+int kw_plan_destroy(kw_plan *plan);
+
 /* Enqueue n >= 0 time steps on the simulation's stream and return. */
 int kw_step(kw_sim *sim, int32_t n);
 
@@ -202,7 +232,9 @@ int64_t kw_gather_bytes(kw_sim *sim, uint32_t what);
  * host (src_is_device == 0) or device memory.  Setting the pressure does not
  * touch the density components; initial-value problems set both. */
 int kw_set_field(kw_sim *sim, int field, const void *src, int src_is_device);
-/* Read one state field (KW_FIELD_*) into dst (nx*ny*nz float32). */
+/* Read one state field (KW_FIELD_*) into dst (nx*ny*nz float32).  The
+ * pressure is transformed back from its spectrum through kw_gather, whose
+ * status is returned unchanged. */
 int kw_gather_field(kw_sim *sim, int field, void *dst, int dst_is_device);
 
 /* Per-kernel-class device timing with HIP events around every launch on the

@@ -4,6 +4,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import threading
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libkw.so")
@@ -44,7 +45,8 @@ KW_FIELD_RHOY = 6
 KW_FIELD_RHOZ = 7
 
 # every symbol include/kw.h declares
-EXPORTS = ("kw_workspace_size", "kw_create", "kw_step", "kw_gather", "kw_gather_bytes",
+EXPORTS = ("kw_workspace_size", "kw_create", "kw_prepare", "kw_plan_workspace_size",
+           "kw_create_prepared", "kw_plan_destroy", "kw_step", "kw_gather", "kw_gather_bytes",
            "kw_set_field", "kw_gather_field", "kw_profile", "kw_stats", "kw_set_graph",
            "kw_set_plan", "kw_state_bytes", "kw_save", "kw_load", "kw_adjoint_workspace_size",
            "kw_adjoint_create", "kw_adjoint_objective", "kw_adjoint_step", "kw_adjoint_source_gradient",
@@ -97,10 +99,16 @@ class KwError(RuntimeError):
 
 
 _lib = None
+_lock = threading.Lock()
 
 
 def load(path: str = LIB_PATH):
     """Load libkw.so (raise if it has not been built)."""
+    with _lock:
+        return _load(path)
+
+
+def _load(path):
     global _lib
     if _lib is not None:
         return _lib
@@ -117,6 +125,15 @@ def load(path: str = LIB_PATH):
     lib.kw_create.restype = C.c_int
     lib.kw_create.argtypes = [P(KwGrid), P(KwMedium), P(KwSource), P(KwSensor), C.c_void_p,
                               C.c_size_t, C.c_void_p, P(C.c_void_p)]
+    lib.kw_prepare.restype = C.c_int
+    lib.kw_prepare.argtypes = [P(KwGrid), P(KwMedium), P(KwSource), P(KwSensor), P(C.c_void_p)]
+    lib.kw_plan_workspace_size.restype = C.c_size_t
+    lib.kw_plan_workspace_size.argtypes = [C.c_void_p]
+    lib.kw_create_prepared.restype = C.c_int
+    lib.kw_create_prepared.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p,
+                                       P(C.c_void_p)]
+    lib.kw_plan_destroy.restype = C.c_int
+    lib.kw_plan_destroy.argtypes = [C.c_void_p]
     lib.kw_step.restype = C.c_int
     lib.kw_step.argtypes = [C.c_void_p, C.c_int32]
     lib.kw_gather.restype = C.c_int

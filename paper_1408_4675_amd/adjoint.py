@@ -39,8 +39,10 @@ class Adjoint:
         if nb == 0:
             raise A.KwError(A.KW_EINVAL, self.lib.kw_last_error().decode())
         self.workspace = torch.empty(int(nb), dtype=torch.uint8, device=sim.device)
+        # ordered before the simulation's stream; close() synchronises that
+        # stream before the workspace goes back to torch (no record_stream:
+        # the simulation may own its stream and destroy it on close)
         sim.stream.wait_stream(torch.cuda.current_stream(sim.device))
-        self.workspace.record_stream(sim.stream)
         h = C.c_void_p()
         A.check(self.lib.kw_adjoint_create(sim.handle, w.ctypes.data_as(C.POINTER(C.c_float)),
                                            self.n_steps, C.c_void_p(self.workspace.data_ptr()),
@@ -72,8 +74,9 @@ class Adjoint:
 
     def close(self):
         if getattr(self, "handle", None):
-            self.lib.kw_adjoint_destroy(self.handle)
+            self.lib.kw_adjoint_destroy(self.handle)     # synchronises the stream
             self.handle = None
+        self.workspace = None
 
 
 def with_drive(scen: Scenario, amp, phase) -> Scenario:

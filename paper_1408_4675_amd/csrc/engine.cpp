@@ -721,34 +721,24 @@ void release(kw_sim *s) {
 
 }  // namespace
 
-// ---------------------------------------------------------------------------
-// C ABI
-// ---------------------------------------------------------------------------
-extern "C" {
+// A prepared set-up: the host state of a simulation (every field of kw_sim
+// but its workspace, stream and device pointers) and the bytes to upload.
+struct kw_plan {
+    kw_sim proto;
+    MediumShape ms;
+    std::vector<std::pair<size_t, std::vector<char>>> up;   // (workspace offset, bytes)
+};
 
-const char *kw_last_error(void) { return g_err.c_str(); }
+namespace {
 
-size_t kw_workspace_size(const kw_grid *grid, const kw_medium *medium, const kw_source *source,
-                         const kw_sensor *sensor) {
-    Counts c;
-    if (validate(grid, medium, source, sensor, c) != KW_OK) return 0;
-    return make_layout(grid, medium, c).total;
-}
-
-int kw_create(const kw_grid *grid, const kw_medium *medium, const kw_source *source,
-              const kw_sensor *sensor, void *dev_workspace, size_t ws_bytes, void *stream,
-              kw_sim **out) {
-    if (!out) return fail(KW_EINVAL, "out must not be NULL");
-    *out = nullptr;
+// Host part of set-up: validation, FFT plans, float64 tables and per-point
+// maps, source and sensor lists.  No HIP call: safe in any thread.
+int prepare(const kw_grid *grid, const kw_medium *medium, const kw_source *source,
+            const kw_sensor *sensor, kw_plan *P) {
     Counts cnt;
     int rc = validate(grid, medium, source, sensor, cnt);
     if (rc != KW_OK) return rc;
     const Layout L = make_layout(grid, medium, cnt);
-    if (!dev_workspace) return fail(KW_EINVAL, "workspace must not be NULL");
-    if ((reinterpret_cast<uintptr_t>(dev_workspace) % kAlign) != 0)
-        return fail(KW_EINVAL, "workspace must be %zu-byte aligned", kAlign);
-    if (ws_bytes < L.total)
-        return fail(KW_ENOMEM, "workspace has %zu bytes, %zu needed", ws_bytes, L.total);
 
     const int nx = grid->nx, ny = grid->ny, nz = grid->nz, M = nx / 2;
     const size_t N = (size_t)nx * ny * nz;
@@ -785,19 +775,15 @@ int kw_create(const kw_grid *grid, const kw_medium *medium, const kw_source *sou
     const bool absorbing = medium->flags & KW_ABSORBING;
     const double y = medium->alpha_power;
 
-    kw_sim *s = new (std::nothrow) kw_sim();
-    if (!s) return fail(KW_EINVAL, "out of host memory");
+    kw_sim *s = &P->proto;
     s->grid = *grid;
     s->flags = medium->flags;
-    s->stream = reinterpret_cast<hipStream_t>(stream);
-    s->ws = reinterpret_cast<char *>(dev_workspace);
     s->L = L;
     s->cnt = cnt;
     s->cfg = cfg;
     s->dt = dt;
     s->c_ref = c_ref;
     s->record_start = sensor ? sensor->record_start : 1;
-    if (s->stream == nullptr) s->graph_steps = 0;   // the legacy stream cannot be captured
     GridDev &g = s->g;
     g.nx = nx;
     g.ny = ny;
@@ -810,7 +796,7 @@ int kw_create(const kw_grid *grid, const kw_medium *medium, const kw_source *sou
     g.y_tau = (float)((y - 2.0) / 2.0);
     g.y_eta = (float)((y - 1.0) / 2.0);
 
-    std::vector<std::pair<size_t, std::vector<char>>> up;   // (offset, bytes)
+    auto &up = P->up;   // (workspace offset, bytes)
     auto put = [&](size_t off, const void *p, size_t n) {
         std::vector<char> v((const char *)p, (const char *)p + n);
         up.emplace_back(off, std::move(v));
@@ -886,6 +872,7 @@ int kw_create(const kw_grid *grid, const kw_medium *medium, const kw_source *sou
                              std::pow(2.0 * kPi * 1.0e6, y);
     const double tan_y = std::tan(kPi * y / 2.0);
     const MediumShape ms = medium_shape(medium);
+    P->ms = ms;
     auto c0_at = [&](size_t i) { return val(medium->c0, medium->c0_scalar, i); };
     auto rho_at = [&](size_t i) { return val(medium->rho0, medium->rho0_scalar, i); };
     auto a_at = [&](size_t i) { return val(medium->alpha0, medium->alpha0_scalar, i) * np_per_db; };
@@ -909,7 +896,7 @@ int kw_create(const kw_grid *grid, const kw_medium *medium, const kw_source *sou
                 std::vector<float> v(N);
                 for (size_t i = 0; i < N; ++i) v[i] = (float)fn(i);
                 put(L.med[which], v.data(), N * sizeof(float));
-                dst.map = s->at<float>(L.med[which]);
+                dst.map = nullptr;              // set when the workspace is bound
                 dst.scalar = 0.0f;
             } else {
                 dst.map = nullptr;
@@ -930,7 +917,6 @@ int kw_create(const kw_grid *grid, const kw_medium *medium, const kw_source *sou
 
     // source
     SourceDev &sd = s->src;
-    sd.drive = s->at<float>(L.drive);
     if (cnt.n_src > 0) {
         const long ns = cnt.n_src;
         const int rows = ny * nz;
@@ -958,12 +944,6 @@ int kw_create(const kw_grid *grid, const kw_medium *medium, const kw_source *sou
         put(L.src_c, cf.data(), ns * sizeof(float));
         put(L.src_ac, ac.data(), ac.size() * sizeof(double));
         put(L.src_as, as.data(), as.size() * sizeof(double));
-        sd.row_ptr = s->at<int>(L.src_row);
-        sd.xpos = s->at<int>(L.src_x);
-        sd.elem = s->at<int>(L.src_e);
-        sd.coef = s->at<float>(L.src_c);
-        sd.amp_cos = s->at<double>(L.src_ac);
-        sd.amp_sin = s->at<double>(L.src_as);
         sd.n_elements = cnt.n_elem;
         sd.omega_dt = 2.0 * kPi * source->freq * dt;
         sd.kind = source->kind;
@@ -977,7 +957,6 @@ int kw_create(const kw_grid *grid, const kw_medium *medium, const kw_source *sou
         s->src_phase.assign(source->phase, source->phase + cnt.n_elem);
         if (cnt.n_samples > 0) {
             put(L.src_sig, source->signal, (size_t)cnt.n_elem * cnt.n_samples * sizeof(float));
-            sd.signal = s->at<float>(L.src_sig);
             sd.n_samples = cnt.n_samples;
         }
     }
@@ -1003,12 +982,44 @@ int kw_create(const kw_grid *grid, const kw_medium *medium, const kw_source *sou
         put(L.sen_x, xp.data(), nsn * sizeof(int));
         put(L.sen_id, id.data(), nsn * sizeof(int));
         put(L.sen_idx, ix.data(), nsn * sizeof(int));
-        se.row_ptr = s->at<int>(L.sen_row);
-        se.xpos = s->at<int>(L.sen_x);
-        se.sid = s->at<int>(L.sen_id);
         se.n_points = (int)nsn;
     } else {
         se.n_points = cnt.sen_all ? (int)N : 0;
+    }
+    if (L.harm) {
+        se.n_harm = cnt.n_harm;
+        se.harm_wdt = 2.0 * kPi * cnt.harm_freq * dt;
+    }
+
+    return KW_OK;
+}
+
+// Point the simulation's device arrays into its workspace (s->ws): the
+// per-point maps the medium needs, source and sensor lists, accumulators,
+// 1D tables, counters and the state and spectral arrays.
+void bind(kw_sim *s, const MediumShape &ms) {
+    const Layout &L = s->L;
+    const Counts &cnt = s->cnt;
+    Medium &md = s->med;
+    Coef *maps[8] = {&md.dtr[0], &md.dtr[1], &md.dtr[2], &md.rho0,
+                     &md.c0sq,   &md.nl,     &md.ta,     &md.tb};
+    for (int i = 0; i < 8; ++i) maps[i]->map = ms.het[i] ? s->at<float>(L.med[i]) : nullptr;
+    SourceDev &sd = s->src;
+    sd.drive = s->at<float>(L.drive);
+    if (cnt.n_src > 0) {
+        sd.row_ptr = s->at<int>(L.src_row);
+        sd.xpos = s->at<int>(L.src_x);
+        sd.elem = s->at<int>(L.src_e);
+        sd.coef = s->at<float>(L.src_c);
+        sd.amp_cos = s->at<double>(L.src_ac);
+        sd.amp_sin = s->at<double>(L.src_as);
+        if (cnt.n_samples > 0) sd.signal = s->at<float>(L.src_sig);
+    }
+    SensorDev &se = s->sen;
+    if (!cnt.sen_all && cnt.n_sen > 0) {
+        se.row_ptr = s->at<int>(L.sen_row);
+        se.xpos = s->at<int>(L.sen_x);
+        se.sid = s->at<int>(L.sen_id);
     }
     if (L.p_max) se.p_max = s->at<float>(L.p_max);
     if (L.p_sum2) se.p_sum2 = s->at<float>(L.p_sum2);
@@ -1017,8 +1028,6 @@ int kw_create(const kw_grid *grid, const kw_medium *medium, const kw_source *sou
     if (L.harm) {
         se.harm = s->at<float>(L.harm);
         se.hw = s->at<float>(L.hw);
-        se.n_harm = cnt.n_harm;
-        se.harm_wdt = 2.0 * kPi * cnt.harm_freq * dt;
     }
     if (L.useries) se.u_series = s->at<float>(L.useries);
 
@@ -1052,6 +1061,33 @@ int kw_create(const kw_grid *grid, const kw_medium *medium, const kw_source *sou
     s->buf.rho_total = L.rho_total ? s->at<float>(L.rho_total) : nullptr;
     for (int i = 0; i < 7; ++i) s->buf.S[i] = s->at<float2>(L.S[i]);
 
+}
+
+// Device part of set-up: bind a prepared plan to a workspace and a stream,
+// choose the launch shapes, upload the tables and maps, zero the state.
+int create_prepared(const kw_plan *P, void *dev_workspace, size_t ws_bytes, void *stream,
+                    kw_sim **out) {
+    if (!out) return fail(KW_EINVAL, "out must not be NULL");
+    *out = nullptr;
+    if (!P) return fail(KW_EINVAL, "plan must not be NULL");
+    const Layout &L = P->proto.L;
+    if (!dev_workspace) return fail(KW_EINVAL, "workspace must not be NULL");
+    if ((reinterpret_cast<uintptr_t>(dev_workspace) % kAlign) != 0)
+        return fail(KW_EINVAL, "workspace must be %zu-byte aligned", kAlign);
+    if (ws_bytes < L.total)
+        return fail(KW_ENOMEM, "workspace has %zu bytes, %zu needed", ws_bytes, L.total);
+    kw_sim *s = new (std::nothrow) kw_sim(P->proto);
+    if (!s) return fail(KW_EINVAL, "out of host memory");
+    s->stream = reinterpret_cast<hipStream_t>(stream);
+    s->ws = reinterpret_cast<char *>(dev_workspace);
+    if (s->stream == nullptr) s->graph_steps = 0;   // the legacy stream cannot be captured
+    bind(s, P->ms);
+    const Counts &cnt = s->cnt;
+    const size_t N = (size_t)s->grid.nx * s->grid.ny * s->grid.nz;
+    SensorDev &se = s->sen;
+    SourceDev &sd = s->src;
+    int rc;
+
     // launch shapes (they depend on the source and sensor set-up above)
     {
         int dev = 0, v = 0;
@@ -1074,7 +1110,7 @@ int kw_create(const kw_grid *grid, const kw_medium *medium, const kw_source *sou
     int dev_count = 0;
     if (hipGetDeviceCount(&dev_count) != hipSuccess || dev_count < 1)
         return bail(fail(KW_EDEVICE, "no HIP device"));
-    for (auto &u : up) {
+    for (auto &u : P->up) {
         hipError_t e = hipMemcpyAsync(s->ws + u.first, u.second.data(), u.second.size(),
                                       hipMemcpyHostToDevice, s->stream);
         if (e != hipSuccess) return bail(fail(KW_EDEVICE, "upload: %s", hipGetErrorString(e)));
@@ -1104,6 +1140,60 @@ int kw_create(const kw_grid *grid, const kw_medium *medium, const kw_source *sou
     if (e != hipSuccess) return bail(fail(KW_EDEVICE, "initialisation: %s", hipGetErrorString(e)));
     *out = s;
     return KW_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *kw_last_error(void) { return g_err.c_str(); }
+
+size_t kw_workspace_size(const kw_grid *grid, const kw_medium *medium, const kw_source *source,
+                         const kw_sensor *sensor) {
+    Counts c;
+    if (validate(grid, medium, source, sensor, c) != KW_OK) return 0;
+    return make_layout(grid, medium, c).total;
+}
+
+int kw_prepare(const kw_grid *grid, const kw_medium *medium, const kw_source *source,
+               const kw_sensor *sensor, kw_plan **out) {
+    if (!out) return fail(KW_EINVAL, "out must not be NULL");
+    *out = nullptr;
+    kw_plan *P = new (std::nothrow) kw_plan();   // value-initialised (zeroed structs)
+    if (!P) return fail(KW_EINVAL, "out of host memory");
+    const int rc = prepare(grid, medium, source, sensor, P);
+    if (rc != KW_OK) {
+        delete P;
+        return rc;
+    }
+    *out = P;
+    return KW_OK;
+}
+
+size_t kw_plan_workspace_size(const kw_plan *plan) { return plan ? plan->proto.L.total : 0; }
+
+int kw_create_prepared(const kw_plan *plan, void *dev_workspace, size_t ws_bytes, void *stream,
+                       kw_sim **out) {
+    return create_prepared(plan, dev_workspace, ws_bytes, stream, out);
+}
+
+int kw_plan_destroy(kw_plan *plan) {
+    delete plan;
+    return KW_OK;
+}
+
+int kw_create(const kw_grid *grid, const kw_medium *medium, const kw_source *source,
+              const kw_sensor *sensor, void *dev_workspace, size_t ws_bytes, void *stream,
+              kw_sim **out) {
+    if (!out) return fail(KW_EINVAL, "out must not be NULL");
+    *out = nullptr;
+    kw_plan P{};   // value-initialised: the plain structs of the prototype start zeroed
+    const int rc = prepare(grid, medium, source, sensor, &P);
+    if (rc != KW_OK) return rc;
+    return create_prepared(&P, dev_workspace, ws_bytes, stream, out);
 }
 
 int kw_step(kw_sim *s, int32_t n) {
@@ -1276,8 +1366,7 @@ int kw_gather_field(kw_sim *s, int field, void *dst, int dst_is_device) {
     const float *src = nullptr;
     switch (field) {
     case KW_FIELD_P:
-        return kw_gather(s, KW_REC_P_FINAL, dst, N * sizeof(float), dst_is_device) == KW_ENONFINITE
-                   ? KW_ENONFINITE : KW_OK;
+        return kw_gather(s, KW_REC_P_FINAL, dst, N * sizeof(float), dst_is_device);
     case KW_FIELD_UX: case KW_FIELD_UY: case KW_FIELD_UZ:
         src = s->buf.u[field - KW_FIELD_UX];
         break;

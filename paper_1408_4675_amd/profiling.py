@@ -1,6 +1,11 @@
 """Summaries of rocprofv3 runs of this library, and a plain copy kernel that
 calibrates the HBM traffic counters.
 
+    python -m paper_1408_4675_amd.profiling run --workload W [--steps K] [--warmup W0] [--eager]
+        K steps of one workload on the GPU, for rocprofv3 to watch: W is
+        tissue_bowl_N (N^3 layered tissue, bowl, all-point p_max / p_rms; N one
+        of the serving sizes or 256) or water_bowl_1024 (1024^3 water, one
+        focal sensor); captured graphs unless --eager
     python -m paper_1408_4675_amd.profiling copy [--mib N] [--reps K]
         a device-to-device copy of N MiB, K times (the reference kernel whose
         FETCH_SIZE / WRITE_SIZE give bytes-per-KiB scale factors)
@@ -203,9 +208,41 @@ def copy_probe(mib: int, reps: int):
     print("copied %d MiB %d times" % (mib, reps), flush=True)
 
 
+def run_workload(name: str, steps: int, warmup: int, eager: bool):
+    import time
+    import torch
+    from . import scenarios as sc
+    from .simulation import Simulation
+    if name.startswith("tissue_bowl_"):
+        scen = sc.tissue_bowl(seed=0, n=int(name.split("_")[-1]), steps=steps)
+    elif name == "water_bowl_1024":
+        scen = sc.water_bowl_large(n=1024, steps=steps)
+    else:
+        raise SystemExit("unknown workload %s" % name)
+    print("workload %s built" % name, flush=True)
+    sim = Simulation(scen, graph_steps=0 if eager else None)
+    sim.step(warmup)
+    sim.synchronize()
+    print("warm-up done", flush=True)
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.synchronize()
+    dt = time.perf_counter() - t0
+    st = sim.stats()
+    sim.close()
+    torch.cuda.synchronize()
+    print("%s: %d steps, %.4f ms per step, nonfinite step %d" % (
+        name, steps, dt / steps * 1e3, st["nonfinite_step"]), flush=True)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(prog="python -m paper_1408_4675_amd.profiling")
     sub = ap.add_subparsers(dest="cmd", required=True)
+    p = sub.add_parser("run")
+    p.add_argument("--workload", required=True)
+    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--warmup", type=int, default=2)
+    p.add_argument("--eager", action="store_true")
     p = sub.add_parser("copy")
     p.add_argument("--mib", type=int, default=1024)
     p.add_argument("--reps", type=int, default=5)
@@ -223,7 +260,9 @@ def main(argv=None):
     p.add_argument("--points", type=int, required=True,
                    help="grid points of the profiled workload (the table applies to that grid only)")
     a = ap.parse_args(argv)
-    if a.cmd == "copy":
+    if a.cmd == "run":
+        run_workload(a.workload, a.steps, a.warmup, a.eager)
+    elif a.cmd == "copy":
         copy_probe(a.mib, a.reps)
     elif a.cmd == "stats":
         with open(a.out, "w") as fh:

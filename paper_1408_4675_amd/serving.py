@@ -3,14 +3,16 @@
 Requests (a Scenario and an arrival time) are admitted while the sum of their
 device footprints (kw_workspace_size, exact) stays within an HBM budget and
 fewer than `max_active` run.  Every admitted simulation keeps its fields
-resident in its own workspace and runs on its own stream, advanced in chunks of
-`chunk_steps` steps (captured HIP graphs); a chunk is enqueued as soon as the
-previous one of that simulation has finished, so simulations of different
-sizes interleave on the GPU (continuous batching).  Set-up (host tables and the
-upload) runs in the scheduling thread, between chunks: the GPU keeps working
-on the chunks already enqueued meanwhile.  (Set-up in worker threads, with
-HIP calls from several host threads at once, was switched off after a heap
-corruption abort in such a run whose cause was not found.)
+resident in its own workspace and runs on a HIP stream of its own, advanced in
+chunks of `chunk_steps` steps (captured HIP graphs); a chunk is enqueued as
+soon as the previous one of that simulation has finished, so simulations of
+different sizes interleave on the GPU (continuous batching).
+
+Set-up is split in two.  The host part (kw_prepare: validation, FFT plans,
+float64 tables and medium maps -- the bulk of the set-up time at 256^3) runs in
+a pool of worker threads as soon as a request arrives, a few requests ahead of
+admission; it makes no HIP call.  The device part (workspace, stream, upload)
+and every other call that touches the GPU run in the scheduling thread only.
 Each result is computed by exactly the same kernels, in the same order, as
 when the request runs alone, so it is bit-for-bit the same.
 
@@ -21,6 +23,7 @@ schedules.
 """
 from __future__ import annotations
 
+import concurrent.futures as cf
 import time
 from dataclasses import dataclass, field
 from typing import Callable, Dict, List, Optional, Sequence
@@ -30,7 +33,7 @@ import torch
 
 from . import _abi as A
 from .scenarios import REC_P_MAX, REC_P_RMS, Request
-from .simulation import Simulation, workspace_size
+from .simulation import Prepared, Simulation, workspace_size
 
 
 @dataclass
@@ -71,7 +74,8 @@ class Server:
     """Continuous-batching scheduler over one GPU."""
 
     def __init__(self, budget_bytes: Optional[int] = None, max_active: int = 8,
-                 chunk_steps: int = 64, keep_outputs: bool = False, device: str = "cuda"):
+                 chunk_steps: int = 64, keep_outputs: bool = False, device: str = "cuda",
+                 prepare_workers: int = 2, prepare_ahead: Optional[int] = None):
         self.device = torch.device(device)
         if budget_bytes is None:
             free, _ = torch.cuda.mem_get_info(self.device)
@@ -80,6 +84,10 @@ class Server:
         self.max_active = max_active
         self.chunk = chunk_steps
         self.keep = keep_outputs
+        self.workers = max(1, int(prepare_workers))
+        # arrived requests whose host preparation may be under way or done but
+        # not yet admitted (each holds its tables and maps in host memory)
+        self.ahead = max(1, int(prepare_ahead if prepare_ahead is not None else max_active))
         self.peak_used = 0             # largest sum of admitted footprints seen
         self.peak_active = 0           # largest number of simulations admitted at once
 
@@ -91,21 +99,34 @@ class Server:
             if foot[r.rid] > self.budget:
                 raise ValueError("request %d needs %d bytes, budget is %d"
                                  % (r.rid, foot[r.rid], self.budget))
-        pending = list(reqs)
+        pending = list(reqs)                 # not admitted, in arrival order
+        prepared: Dict[int, cf.Future] = {}  # host preparation of pending requests
         active: List[_Active] = []
         results: List[Result] = []
         used = 0
+        pool = cf.ThreadPoolExecutor(max_workers=self.workers)
         t0 = time.perf_counter()
         try:
             while pending or active:
                 now = time.perf_counter() - t0
-                # admission: arrived, a slot free, footprint within budget (in order)
-                while (pending and pending[0].arrival <= now
+                # host preparation of the first arrived requests (no device calls)
+                for r in pending[: self.ahead]:
+                    if r.arrival > now:
+                        break
+                    if r.rid not in prepared:
+                        prepared[r.rid] = pool.submit(Prepared, r.scenario)
+                # admission: arrived and prepared, a slot free, footprint within
+                # budget, strictly in arrival order
+                while (pending and pending[0].rid in prepared and prepared[pending[0].rid].done()
                        and len(active) < self.max_active
                        and used + foot[pending[0].rid] <= self.budget):
                     r = pending.pop(0)
+                    prep = prepared.pop(r.rid).result()
                     used += foot[r.rid]
-                    active.append(self._create(r, now))
+                    try:
+                        active.append(self._create(r, now, prep))
+                    finally:
+                        prep.close()
                     self.peak_used = max(self.peak_used, used)
                     self.peak_active = max(self.peak_active, len(active))
                 progressed = False
@@ -131,16 +152,21 @@ class Server:
                     if on_done:
                         on_done(res)
                 if not progressed:
-                    # nothing to issue: wait briefly for an arrival or a chunk to end
+                    # nothing to issue: wait briefly for an arrival, a preparation
+                    # or a chunk to end
                     nxt = pending[0].arrival - (time.perf_counter() - t0) if pending else 1.0
                     time.sleep(max(0.0, min(nxt, 2e-4)))
         finally:
+            pool.shutdown(wait=True)
+            for f in prepared.values():
+                if f.done() and f.exception() is None:
+                    f.result().close()
             for a in active:
                 a.sim.close()
         return sorted(results, key=lambda r: r.rid)
 
-    def _create(self, r: Request, now: float) -> _Active:
-        sim = Simulation(r.scenario, device=str(self.device))
+    def _create(self, r: Request, now: float, prep: Optional[Prepared] = None) -> _Active:
+        sim = Simulation(r.scenario, device=str(self.device), prepared=prep)
         return _Active(r, sim, r.scenario.steps, now)
 
 

@@ -8,6 +8,7 @@ and the stream, libkw.so does all the work.
 from __future__ import annotations
 
 import ctypes as C
+import os
 from typing import Optional
 
 import numpy as np
@@ -93,28 +94,102 @@ def workspace_size(sc: Scenario) -> int:
     return int(n)
 
 
+class Prepared:
+    """Host part of a simulation's set-up (kw_prepare): validation, FFT plans,
+    float64 operator tables and medium maps.  It makes no device call, so it
+    may be built in any thread; Simulation(..., prepared=p) then only uploads."""
+
+    def __init__(self, sc: Scenario):
+        self.lib = A.load()
+        self.scenario = sc
+        m = _Marshalled(sc)
+        handle = C.c_void_p()
+        A.check(self.lib.kw_prepare(*m.args(), C.byref(handle)))
+        self.handle = handle
+        self.workspace_bytes = int(self.lib.kw_plan_workspace_size(handle))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.kw_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_hip = None
+
+
+def _hip_runtime():
+    """The HIP runtime already in the process (torch's, which libkw.so binds
+    to as well): a stream of our own is created there."""
+    global _hip
+    if _hip is None:
+        A.load()
+        lib = C.CDLL("libamdhip64.so.7", mode=os.RTLD_NOLOAD | os.RTLD_GLOBAL)
+        lib.hipStreamCreateWithFlags.argtypes = [C.POINTER(C.c_void_p), C.c_uint]
+        lib.hipStreamCreateWithFlags.restype = C.c_int
+        lib.hipStreamDestroy.argtypes = [C.c_void_p]
+        lib.hipStreamDestroy.restype = C.c_int
+        _hip = lib
+    return _hip
+
+
+_HIP_STREAM_NON_BLOCKING = 1
+
+
+def _own_stream(device: torch.device):
+    """A new non-blocking HIP stream at the default priority (torch.cuda.Stream
+    hands out one of 32 pooled streams per device in turn, so simulations that
+    live long enough would end up sharing one)."""
+    hip = _hip_runtime()
+    handle = C.c_void_p()
+    with torch.cuda.device(device):
+        rc = hip.hipStreamCreateWithFlags(C.byref(handle), _HIP_STREAM_NON_BLOCKING)
+    if rc != 0:
+        raise A.KwError(A.KW_EDEVICE, "hipStreamCreateWithFlags failed (%d)" % rc)
+    return handle.value, torch.cuda.ExternalStream(handle.value, device=device)
+
+
 class Simulation:
+    """One simulation on the GPU.  It runs on a HIP stream of its own (or on
+    `stream` when one is given); the device workspace is a torch tensor."""
+
     def __init__(self, sc: Scenario, device: str = "cuda", stream: Optional[torch.cuda.Stream] = None,
-                 graph_steps: Optional[int] = None, tune: bool = True):
+                 graph_steps: Optional[int] = None, tune: bool = True,
+                 prepared: Optional[Prepared] = None):
         self.lib = A.load()
         self.scenario = sc
         self.device = torch.device(device)
-        m = _Marshalled(sc)
-        nbytes = self.lib.kw_workspace_size(*m.args())
-        if nbytes == 0:
-            raise A.KwError(A.KW_EINVAL, self.lib.kw_last_error().decode())
-        self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
-        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
-        # the workspace is allocated on the current stream; order it before the sim's stream
-        self.stream.wait_stream(torch.cuda.current_stream(self.device))
-        # keep the caching allocator from reusing the workspace while the
-        # simulation's stream may still use it
-        self.workspace.record_stream(self.stream)
-        handle = C.c_void_p()
-        A.check(self.lib.kw_create(*m.args(), C.c_void_p(self.workspace.data_ptr()),
-                                   C.c_size_t(nbytes), C.c_void_p(self.stream.cuda_stream),
-                                   C.byref(handle)))
-        self.handle = handle
+        self.handle = None
+        self._own = None
+        own_prep = prepared is None
+        prep = Prepared(sc) if own_prep else prepared
+        try:
+            nbytes = prep.workspace_bytes
+            self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+            if stream is None:
+                self._own, self.stream = _own_stream(self.device)
+            else:
+                self.stream = stream
+            # the workspace is allocated on the current stream: order it before the
+            # simulation's stream.  No record_stream: close() synchronises the
+            # simulation's stream before the workspace is released
+            self.stream.wait_stream(torch.cuda.current_stream(self.device))
+            handle = C.c_void_p()
+            A.check(self.lib.kw_create_prepared(prep.handle, C.c_void_p(self.workspace.data_ptr()),
+                                                C.c_size_t(nbytes), C.c_void_p(self.stream.cuda_stream),
+                                                C.byref(handle)))
+            self.handle = handle
+        except Exception:
+            self.close()
+            raise
+        finally:
+            if own_prep:
+                prep.close()
         self.npts = sc.grid.npts
         if graph_steps is not None:
             A.check(self.lib.kw_set_graph(self.handle, int(graph_steps)))
@@ -218,10 +293,18 @@ class Simulation:
         self.stream.synchronize()
 
     def close(self):
+        """Wait for the simulation's work, free its host state, release the
+        workspace and destroy the stream it owns (in that order: the workspace
+        goes back to torch only once nothing on the stream can touch it)."""
         if getattr(self, "handle", None):
             self.stream.synchronize()
             self.lib.kw_destroy(self.handle)
             self.handle = None
+        self.workspace = None
+        if getattr(self, "_own", None):
+            self.stream.synchronize()
+            _hip_runtime().hipStreamDestroy(C.c_void_p(self._own))
+            self._own = None
 
     def __del__(self):
         try:

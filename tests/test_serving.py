@@ -1,5 +1,7 @@
 """Serving loop: results identical alone and mixed, admission within the
 HBM budget (GPU), and the trace and summary logic (CPU)."""
+import threading
+
 import numpy as np
 import pytest
 
@@ -36,10 +38,35 @@ def test_summary_percentiles():
 
 
 @pytest.mark.gpu
-@pytest.mark.skip(reason="a 100-request serving run with set-up in worker threads aborted on "
-                         "the GPU with a host heap corruption of unknown cause; set-up is now "
-                         "serialised (a change made without a shown cause), so the serving "
-                         "path stays off the GPU until the cause is found")
+def test_live_simulations_have_distinct_streams():
+    """torch.cuda.Stream() hands out one of 32 pooled streams per device in
+    turn, so the 33rd is the 1st again; a Simulation takes a HIP stream of its
+    own, so 34 simulations alive at once run on 34 streams, and each still
+    gives the result it gives alone."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1408_4675_amd.simulation import Simulation
+    print("\n[case] 34 live 16^3 simulations, stream handles", flush=True)
+    pool = [torch.cuda.Stream() for _ in range(33)]
+    assert pool[0].cuda_stream == pool[32].cuda_stream          # the pooled streams repeat
+    scen = sc.small_case(16, 16, 16, seed=4, steps=6)
+    sims = [Simulation(scen, tune=False) for _ in range(34)]
+    try:
+        handles = [s.stream.cuda_stream for s in sims]
+        assert len(set(handles)) == len(sims)
+        assert not set(handles) & {p.cuda_stream for p in pool}
+        for s in sims:
+            s.step(scen.steps)
+        outs = [s.gather(sc.REC_P_MAX, device=False) for s in sims]
+        for o in outs[1:]:
+            assert np.array_equal(o, outs[0])
+    finally:
+        for s in sims:
+            s.close()
+
+
+@pytest.mark.gpu
 def test_mixed_results_equal_alone_and_budget_holds():
     import torch
     if not torch.cuda.is_available():
@@ -51,7 +78,10 @@ def test_mixed_results_equal_alone_and_budget_holds():
     print("\n[case] serving: 8 requests of 32^3-64^3, mixed vs alone", flush=True)
     alone = {r.rid: r for r in run_fifo(reqs, keep_outputs=True)}
     foot = max(workspace_size(r.scenario) for r in reqs)
-    srv = Server(budget_bytes=2 * foot + 1, max_active=4, chunk_steps=16, keep_outputs=True)
+    # host preparation in two worker threads (no device calls there); every
+    # device call in this thread
+    srv = Server(budget_bytes=2 * foot + 1, max_active=4, chunk_steps=16, keep_outputs=True,
+                 prepare_workers=2)
     mixed = srv.run(reqs)
     assert srv.peak_used <= 2 * foot + 1
     assert srv.peak_active >= 2
@@ -66,13 +96,28 @@ def test_mixed_results_equal_alone_and_budget_holds():
 def test_scheduler_admission_budget_and_chunks(monkeypatch):
     """The scheduler alone, on a stand-in for the simulation (no GPU): requests
     are admitted in arrival order within the footprint budget and the slot
-    limit, every request runs exactly its steps in chunks, and each finishes."""
+    limit, every request runs exactly its steps in chunks, and each finishes.
+    The host preparation (the library's kw_prepare, which makes no device
+    call) runs in worker threads; the device set-up only in the scheduling
+    thread."""
     import paper_1408_4675_amd.serving as S
+    from paper_1408_4675_amd.simulation import workspace_size as real_workspace_size
 
-    log = {"active": 0, "peak": 0, "steps": {}, "order": []}
+    log = {"active": 0, "peak": 0, "steps": {}, "order": [], "prepare_threads": set()}
+
+    main_thread = threading.get_ident()
+
+    class RecordingPrepared(S.Prepared):
+        # the real host-only preparation (kw_prepare runs on the CPU), noting its thread
+        def __init__(self, scen):
+            log["prepare_threads"].add(threading.get_ident())
+            super().__init__(scen)
 
     class FakeSim:
-        def __init__(self, scen, device="cuda"):
+        def __init__(self, scen, device="cuda", prepared=None):
+            assert threading.get_ident() == main_thread      # device set-up: scheduling thread only
+            assert isinstance(prepared, S.Prepared) and prepared.handle
+            assert prepared.workspace_bytes == real_workspace_size(scen)
             self.scen = scen
             self.stream = None
             log["active"] += 1
@@ -101,15 +146,16 @@ def test_scheduler_admission_budget_and_chunks(monkeypatch):
         r.scenario.name = "r%d" % i
     foot = {id(r.scenario): (100 if r.scenario.grid.nx == 32 else 250) for r in reqs}
     monkeypatch.setattr(S, "Simulation", FakeSim)
+    monkeypatch.setattr(S, "Prepared", RecordingPrepared)
     monkeypatch.setattr(S, "workspace_size", lambda scen: foot[id(scen)])
     monkeypatch.setattr(S.torch.cuda, "Event", FakeEvent)
-    monkeypatch.setattr(S.A, "load", lambda *a, **k: None)
     srv = S.Server(budget_bytes=600, max_active=3, chunk_steps=16)
     res = srv.run(reqs)
     assert len(res) == 12 and log["active"] == 0
     assert log["order"] == ["r%d" % i for i in range(12)]          # arrival order
     assert srv.peak_active <= 3 and log["peak"] <= 3
     assert srv.peak_used <= 600
+    assert log["prepare_threads"] and main_thread not in log["prepare_threads"]
     for i, r in enumerate(reqs):
         assert log["steps"]["r%d" % i] == r.scenario.steps
     with pytest.raises(ValueError):
