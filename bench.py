@@ -230,6 +230,29 @@ def serving_bench(n_requests, rate=20.0, seed=0):
     return out
 
 
+def serving_summary(n_requests, rate=20.0, seed=0):
+    """The latency half of the metric, measured in the default run: the
+    first `n_requests` requests of the Poisson serving trace (20/s, 64^3-256^3
+    tissue, 300-1500 steps) served with continuous batching and one at a time
+    (FIFO), p50 / p99 latency from arrival to gathered result, and
+    throughput."""
+    from paper_1408_4675_amd import scenarios as sc
+    from paper_1408_4675_amd.serving import Server, run_fifo, summarize
+    log("serving: building %d requests" % n_requests)
+    reqs = sc.serving_trace(seed=seed, n_requests=n_requests, rate=rate, medium_pool=2)
+    done = lambda tag: (lambda r: log("serving %s: request %d done" % (tag, r.rid)))
+    srv = Server(max_active=8, chunk_steps=64)
+    b = summarize(srv.run(reqs, on_done=done("batched")))
+    f = summarize(run_fifo(reqs, on_done=done("fifo")))
+    keys = ("p50_latency_s", "p99_latency_s", "requests_per_s", "point_updates_per_s",
+            "makespan_s")
+    return dict(workload="first %d requests of the Poisson trace (seed %d, %.0f/s offered, "
+                         "64^3-256^3 tissue, 300-1500 steps)" % (n_requests, seed, rate),
+                batched={k: round(b[k], 4) for k in keys},
+                fifo={k: round(f[k], 4) for k in keys},
+                peak_active=srv.peak_active)
+
+
 def adjoint_bench(checkpoint_every=50, fd_params=4):
     """Gradient of J = mean intensity in a 2 mm sphere at the focus minus the
     mean outside, with respect to the 64 element amplitudes and phases, on the
@@ -290,6 +313,9 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the 1024^3 item")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--large-steps", type=int, default=100)
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving latency item")
+    ap.add_argument("--serving-requests", type=int, default=30,
+                    help="requests of the serving trace in the default run's latency item")
     ap.add_argument("--serving", type=int, default=0, metavar="N",
                     help="instead of the step benchmark, serve the first N requests of the "
                          "Poisson trace (20/s, 64^3-256^3 tissue) batched and one at a time")
@@ -382,6 +408,11 @@ def main():
                                 per_class=bper)
         except Exception as e:   # report, but keep the headline line
             out["large"] = dict(error=str(e))
+    if not args.no_serving:
+        try:
+            out["serving"] = serving_summary(args.serving_requests)
+        except Exception as e:   # report, but keep the headline line
+            out["serving"] = dict(error=str(e))
     out["paper_context"] = PAPER_CONTEXT
     if not args.no_cpu:
         log("timing the CPU oracle baseline")

@@ -54,10 +54,10 @@ class AdjointOracle:
             raise ValueError("the recording window is empty")
         self.J = None
 
-    def forward(self) -> float:
+    def forward(self, progress=None) -> float:
         o = self.o
         o.tape = []
-        o.step(self.steps)
+        o.step(self.steps, progress)
         rc = o.rho0 * o.c0
         J = 0.0
         for t in o.tape:
@@ -70,7 +70,8 @@ class AdjointOracle:
         o = self.o
         return o.ift(m * o.ft(f))
 
-    def backward(self) -> dict:
+    def backward(self, progress=None) -> dict:
+        """progress(k), if given, is called after the k-th reverse step."""
         o = self.o
         if self.J is None:
             self.forward()
@@ -131,6 +132,8 @@ class AdjointOracle:
                 ub[a] = q * q * ub[a]
             # Eq. (4a): transpose of the gradient
             pb = sum(self._op(np.conj(o.d_plus[a] * o.kappa), gb[a]) for a in range(3))
+            if progress is not None:
+                progress(self.steps - n)
         theta = 2.0 * np.pi * src["freq"] * (np.arange(self.steps) + 0.5) * dt
         ph = theta[:, None] + src["phase"][None, :]
         grad_amp = np.sum(dJds * np.sin(ph), axis=0)

@@ -264,9 +264,12 @@ class Oracle:
         """Eq. (4c): d u_xi / d xi back on the regular grid, per component."""
         return [self.ift(self.d_minus[a] * self.kappa * self.ft(u[a])) for a in range(3)]
 
-    def step(self, nsteps: int = 1):
-        for _ in range(nsteps):
+    def step(self, nsteps: int = 1, progress=None):
+        """Advance nsteps steps; progress(i), if given, is called after each."""
+        for i in range(nsteps):
             self._one_step()
+            if progress is not None:
+                progress(i + 1)
 
     def _one_step(self):
         dt = self.dt

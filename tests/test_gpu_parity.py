@@ -321,6 +321,28 @@ def test_parity_long_axes(kw, shape):
         assert e <= tol, (k, e)
 
 
+# Homogeneous absorbing water (scalar c0^2 tau, c0^2 eta): the merged
+# absorption z pass (one inverse transform for both terms of Eq. (8)), which
+# the 1024^3 water workload runs at 1024 points in half-width tiles, and the
+# pressure kernel reading the merged spectrum with the mask-sensor code
+# (kw_xeos<..., SENS, MERGED>, fixed x engine for nx >= 32)
+MERGED = [(32, 8, 1024), (48, 6, 1024), (32, 1024, 6), (1024, 8, 8), (64, 36, 30)]
+
+
+@pytest.mark.parametrize("shape", MERGED, ids=["%dx%dx%d" % s for s in MERGED])
+def test_parity_merged_absorption(kw, shape):
+    nx, ny, nz = shape
+    scen = sc.small_case(nx, ny, nz, seed=13, heterogeneous=False, nonlinear=True,
+                         absorbing=True, pml=2, steps=8, sensor_mask=True, amp=2e6)
+    scen = scen.replace(name="merged_" + scen.name)
+    sim, orc = _run_both(kw, scen, 8)
+    st = sim.stats()
+    assert st["fft_inverse_per_step"] == 7            # the merged path ran
+    errs, tol = compare_outputs(sim, orc, scen, REPORT)
+    for k, e in errs.items():
+        assert e <= tol, (k, e)
+
+
 @pytest.mark.slow
 def test_water_bowl_1024_full_size_properties(kw):
     """The 1024^3 homogeneous water grid with the 3 MHz bowl, in the launch
