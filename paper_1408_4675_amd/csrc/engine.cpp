@@ -795,6 +795,7 @@ int prepare(const kw_grid *grid, const kw_medium *medium, const kw_source *sourc
     g.dt = (float)dt;
     g.y_tau = (float)((y - 2.0) / 2.0);
     g.y_eta = (float)((y - 1.0) / 2.0);
+    g.dkz = (float)(2.0 * kPi / (grid->dz * nz));
 
     auto &up = P->up;   // (workspace offset, bytes)
     auto put = [&](size_t off, const void *p, size_t n) {
@@ -1571,7 +1572,7 @@ namespace {
 
 struct AdjLayout {
     size_t fld[16];          // pb, ub x3, rb x3, d x3, T x3, pf, w, rbt
-    size_t dJds, obj, flat, elem, coef, corr, total;
+    size_t dJds, obj, flat, elem, coef, corr, share, eptr, epts, partials, total;
 };
 
 AdjLayout adj_layout(const kw_sim *s, int n_steps) {
@@ -1586,6 +1587,10 @@ AdjLayout adj_layout(const kw_sim *s, int n_steps) {
     L.elem = cv.take(std::max<size_t>(ns, 1) * sizeof(int));
     L.coef = cv.take(std::max<size_t>(ns, 1) * sizeof(float));
     L.corr = cv.take(3 * std::max<size_t>(ns, 1) * sizeof(float));
+    L.share = cv.take(std::max<size_t>(ns, 1) * sizeof(double));
+    L.eptr = cv.take((size_t)(std::max(1, s->cnt.n_elem) + 1) * sizeof(int));
+    L.epts = cv.take(std::max<size_t>(ns, 1) * sizeof(int));
+    L.partials = cv.take((size_t)adj_objective_blocks(s->g) * sizeof(double));
     L.total = cv.off;
     return L;
 }
@@ -1660,6 +1665,19 @@ int kw_adjoint_create(kw_sim *s, const float *weights, int32_t n_steps, void *de
     a.src_elem = reinterpret_cast<int *>(ws + L.elem);
     a.src_coef = reinterpret_cast<float *>(ws + L.coef);
     a.corr = reinterpret_cast<float *>(ws + L.corr);
+    a.share = reinterpret_cast<double *>(ws + L.share);
+    a.elem_ptr = reinterpret_cast<int *>(ws + L.eptr);
+    a.elem_pts = reinterpret_cast<int *>(ws + L.epts);
+    a.partials = reinterpret_cast<double *>(ws + L.partials);
+    // the source points of each element, in increasing order (the fixed order
+    // in which their shares of dJ/ds_e are summed)
+    std::vector<int> eptr(a.n_elem + 1, 0), epts(s->src_flat.size());
+    for (int e : s->src_elem) eptr[e + 1]++;
+    for (int e = 0; e < a.n_elem; ++e) eptr[e + 1] += eptr[e];
+    {
+        std::vector<int> fill(eptr.begin(), eptr.end() - 1);
+        for (size_t k = 0; k < s->src_elem.size(); ++k) epts[fill[s->src_elem[k]]++] = (int)k;
+    }
     const size_t N = (size_t)s->grid.nx * s->grid.ny * s->grid.nz;
     hipStream_t st = s->stream;
     auto bail = [&](hipError_t e) {
@@ -1674,7 +1692,9 @@ int kw_adjoint_create(kw_sim *s, const float *weights, int32_t n_steps, void *de
     const size_t ns = s->src_flat.size();
     if ((e = hipMemcpyAsync(ws + L.flat, s->src_flat.data(), ns * sizeof(int), hipMemcpyHostToDevice, st)) != hipSuccess ||
         (e = hipMemcpyAsync(ws + L.elem, s->src_elem.data(), ns * sizeof(int), hipMemcpyHostToDevice, st)) != hipSuccess ||
-        (e = hipMemcpyAsync(ws + L.coef, s->src_coef.data(), ns * sizeof(float), hipMemcpyHostToDevice, st)) != hipSuccess)
+        (e = hipMemcpyAsync(ws + L.coef, s->src_coef.data(), ns * sizeof(float), hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(ws + L.eptr, eptr.data(), eptr.size() * sizeof(int), hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(ws + L.epts, epts.data(), ns * sizeof(int), hipMemcpyHostToDevice, st)) != hipSuccess)
         return bail(e);
     for (int i = 0; i < 7; ++i)   // pb, ub, rb start at zero
         if ((e = launch_fill(st, F(i), N, 0.0f)) != hipSuccess) return bail(e);
@@ -1726,8 +1746,8 @@ int kw_adjoint_objective(kw_adj *adj, double *J) {
     if (s->steps != adj->n_steps)
         return fail(KW_ESTATE, "the simulation holds step %ld, the objective needs step %d",
                     s->steps, adj->n_steps);
-    KW_HIP(hipMemsetAsync(adj->a.obj, 0, sizeof(double), s->stream));
-    KW_HIP(launch_adj_objective(s->stream, s->g, adj->a.w, s->sen.p_sum2, adj->a.obj));
+    KW_HIP(launch_adj_objective(s->stream, s->g, adj->a.w, s->sen.p_sum2, adj->a.partials,
+                                adj->a.obj));
     KW_HIP(hipMemcpyAsync(J, adj->a.obj, sizeof(double), hipMemcpyDeviceToHost, s->stream));
     KW_HIP(hipStreamSynchronize(s->stream));
     return KW_OK;

@@ -11,8 +11,11 @@
 // adjoints pb, ub, rb of (p', u', rho') the kernels below form, in order:
 //   eos:  pbar = pb + w p' (recorded steps),  rbt = (c0^2 + 2 nl rho) pbar,
 //         T0 = ta pbar, T1 = tb pbar           (then T0 <- A T0, T1 <- B T1 spectrally)
-//   src:  at source points, R_xi = rb_xi + rbt + T1, dJ/ds_e(n) += coef sum_xi R_xi
-//         and the correction 2 dt R_xi src / den_xi of the divergence adjoint
+//   src:  at source points, R_xi = rb_xi + rbt + T1, the point's share coef sum_xi R_xi
+//         of dJ/ds_e(n) and the correction 2 dt R_xi src / den_xi of the
+//         divergence adjoint; the shares of each element are then summed in a
+//         fixed order (no floating-point atomics: the gradient is repeatable
+//         bit for bit)
 //   den:  R_xi = rb_xi + rbt + T1,  rb_xi <- R_xi q^2 / den_xi,
 //         d_xi <- -R_xi (q dt rho0 + 2 dt rho_xi') / den_xi + rho0 T0
 //   (spectral: T_xi = transpose-divergence of d_xi)
@@ -84,7 +87,33 @@ __global__ void __launch_bounds__(kThreads) kw_adj_src(GridDev g, Medium m, AdjD
         }
         a.corr[(size_t)x * a.n_src + k] = c;
     }
-    atomicAdd(&a.dJds[(size_t)n * a.n_elem + e], (double)coef * (double)rsum);
+    a.share[k] = (double)coef * (double)rsum;
+}
+
+// Sum of block-sized slices in a fixed order: each thread adds the values it
+// strides over, then a fixed tree over the block.  Called by every thread.
+__device__ __forceinline__ double block_sum(double v, double *part) {
+    part[threadIdx.x] = v;
+    __syncthreads();
+    for (int h = kThreads / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+        __syncthreads();
+    }
+    const double r = part[0];
+    __syncthreads();
+    return r;
+}
+
+// dJ/ds_e(n) = sum of the shares of element e's points (one block per element,
+// points in the order of the element's list)
+__global__ void __launch_bounds__(kThreads) kw_adj_src_sum(AdjDev a, int n) {
+    __shared__ double part[kThreads];
+    const int e = blockIdx.x;
+    double acc = 0.0;
+    for (int j = a.elem_ptr[e] + (int)threadIdx.x; j < a.elem_ptr[e + 1]; j += kThreads)
+        acc += a.share[a.elem_pts[j]];
+    const double total = block_sum(acc, part);
+    if (threadIdx.x == 0) a.dJds[(size_t)n * a.n_elem + e] = total;
 }
 
 __global__ void __launch_bounds__(kThreads) kw_adj_den(GridDev g, Tables t, Medium m, AdjDev a,
@@ -156,30 +185,40 @@ __global__ void __launch_bounds__(kThreads) kw_adj_sum(GridDev g, AdjDev a) {
 }
 
 // J = 1/2 sum_i w'(i) sum2(i) with w' = 2 w / (rho0 c0 N_w): block sums in
-// float64, one atomic per block
+// float64 into partials[blockIdx.x], then one block adds the partials in order
 __global__ void __launch_bounds__(kThreads) kw_adj_objective(GridDev g, const float *w,
-                                                              const float *sum2, double *out) {
+                                                              const float *sum2, double *partials) {
     __shared__ double part[kThreads];
     const size_t N = npoints(g);
     double acc = 0.0;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
          i += (size_t)gridDim.x * blockDim.x)
         acc += 0.5 * (double)w[i] * (double)sum2[i];
-    part[threadIdx.x] = acc;
-    __syncthreads();
-    for (int h = kThreads / 2; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) atomicAdd(out, part[0]);
+    const double total = block_sum(acc, part);
+    if (threadIdx.x == 0) partials[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(kThreads) kw_adj_partials(const double *partials, int n,
+                                                             double *out) {
+    __shared__ double part[kThreads];
+    double acc = 0.0;
+    for (int j = threadIdx.x; j < n; j += kThreads) acc += partials[j];
+    const double total = block_sum(acc, part);
+    if (threadIdx.x == 0) *out = total;
 }
 
 // launchers -----------------------------------------------------------------------
 
+int adj_objective_blocks(const GridDev &g) { return (int)grid_for((size_t)g.nx * g.rows).x; }
+
 hipError_t launch_adj_objective(hipStream_t s, const GridDev &g, const float *w,
-                                const float *sum2, double *out) {
+                                const float *sum2, double *partials, double *out) {
     const size_t N = (size_t)g.nx * g.rows;
-    hipLaunchKernelGGL(kw_adj_objective, grid_for(N), dim3(kThreads), 0, s, g, w, sum2, out);
+    const dim3 grid = grid_for(N);
+    hipLaunchKernelGGL(kw_adj_objective, grid, dim3(kThreads), 0, s, g, w, sum2, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kw_adj_partials, dim3(1), dim3(kThreads), 0, s, partials, (int)grid.x, out);
     return hipGetLastError();
 }
 
@@ -204,6 +243,9 @@ hipError_t launch_adj_src(hipStream_t s, const GridDev &g, const Medium &m, cons
     if (a.n_src == 0) return hipSuccess;
     hipLaunchKernelGGL(kw_adj_src, dim3((a.n_src + kThreads - 1) / kThreads), dim3(kThreads), 0, s,
                        g, m, a, src, n);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kw_adj_src_sum, dim3(a.n_elem), dim3(kThreads), 0, s, a, n);
     return hipGetLastError();
 }
 

@@ -162,6 +162,28 @@ __device__ __forceinline__ void stage_table(float2 *dst, const float2 *__restric
     for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
 }
 
+// XCD-aware order of the column passes.  Workgroups are dispatched round-robin
+// over the 8 XCDs (XCD = workgroup id mod 8), each with an L2 of its own.
+// Blocks that read the same 128-byte lines -- G consecutive tiles narrower than
+// a line, and R blocks of one tile that each read its input -- are given
+// consecutive dispatch slots on one XCD, so that all but the first find the
+// lines in that XCD's L2 instead of fetching them again.  Workgroup B maps to
+// tile block `blk` and repeat `r`; false for the padding of the grid (whole
+// groups on every XCD).
+__host__ __device__ inline int xcd_grid(int nblk, int G, int R) {
+    const int groups = (nblk + G - 1) / G;
+    return (groups + 7) / 8 * 8 * G * R;
+}
+__device__ __forceinline__ bool xcd_order(int B, int G, int R, int nblk, int &blk, int &r) {
+    const int x = B & 7, q = B >> 3, GR = G * R;
+    const int w = q % GR;
+    blk = ((q / GR) * 8 + x) * G + w / R;
+    r = w % R;
+    return blk < nblk;
+}
+// tiles sharing a 128-byte line: G = 16 / tb for tiles under 16 columns
+__host__ __device__ inline int line_group(int tb) { return tb < 16 ? 16 / tb : 1; }
+
 // Drive value s_e of element e in step n, at t = (n + t_offset) dt (n + 1/2
 // for the mass source of Eq. (4d), n for the force of Eq. (4b), n + 1 for a
 // pressure source): a_e sin(omega t + phi_e) = a_e cos(phi_e) sin(omega t)
@@ -181,6 +203,7 @@ struct YArgs {
     FftPlan plan;            // forward plan, or the reversed plan for the inverse
     const float2 *tw;
     int tb;
+    int ntiles, nz;          // column tiles per y-z plane row, z planes
     // prologue (first kernel of a step): advance the step counter and
     // evaluate the drive value of every source element at t = (n + 1/2) dt
     int prologue;
@@ -203,15 +226,18 @@ __global__ void __launch_bounds__(MAXT) kw_ypass(YArgs a) {
     float2 *const sh = lds_all + a.ny;       // column tile
     const int tid = threadIdx.x;
     const int b = tid % a.tb, t = tid / a.tb;
-    const int col = blockIdx.x * a.tb + b;
+    int blk, rep_;
+    if (!xcd_order(blockIdx.x, line_group(a.tb), 1, a.ntiles * a.nz, blk, rep_)) return;
+    const int tile = blk % a.ntiles, iz = blk / a.ntiles;
+    const int col = tile * a.tb + b;
     const bool ok = col < a.M;
     // element (row t + m step, column col) of this block's tile: uniform base
     // base + m step M, lane offset (t M + b) elements
-    float2 *const base = pick3(a.f, (int)blockIdx.z) + (size_t)blockIdx.y * a.ny * a.M +
-                         (size_t)blockIdx.x * a.tb;
+    float2 *const base = pick3(a.f, (int)blockIdx.z) + (size_t)iz * a.ny * a.M +
+                         (size_t)tile * a.tb;
     const uint32_t lane = (uint32_t)(t * a.M + b) * 8u;
 
-    if (a.prologue && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0) {
+    if (a.prologue && blk == 0 && blockIdx.z == 0) {
         const int n = *a.cnt.step;
         __syncthreads();
         if (tid == 0) *a.cnt.step = n + 1;
@@ -235,7 +261,7 @@ __global__ void __launch_bounds__(MAXT) kw_ypass(YArgs a) {
     }
     stage_table(tws, a.tw, ny);
     __syncthreads();
-    const bool tile0 = blockIdx.x == 0;          // block-uniform
+    const bool tile0 = tile == 0;                // block-uniform
     if (INV && tile0) {
         // repack column 0: C(ky) = A(ky) + i B(ky), using A(-ky) = conj A(ky)
         if (b == 0) {
@@ -321,12 +347,17 @@ struct ZArgs {
     float sa, sb;            // ABSM: c0^2 tau and -c0^2 eta of a homogeneous medium
 };
 
+// kz of FFT index iz (Eq. (5)): m 2 pi / (nz dz), m = iz - nz above the middle
+__device__ __forceinline__ float kz_of(const GridDev &g, int iz) {
+    return (float)(iz <= (g.nz - 1) / 2 ? iz : iz - g.nz) * g.dkz;
+}
+
 // multiplier of output o at (kx index ix (M = Nyquist), ky index iy, kz index iz)
-// kzl, dzl: kz and the z factor D+-_z of the mode, staged in LDS
+// dzl: the z factor D+-_z of the mode, staged in LDS
 template <int MODE>
 __device__ __forceinline__ float2 z_operator(const ZArgs &a, int o, int ix, int iy, int iz,
-                                             const float *kzl, const float2 *dzl) {
-    const float kx = a.t.kx[ix], ky = a.t.ky[iy], kz = kzl[iz];
+                                             const float2 *dzl) {
+    const float kx = a.t.kx[ix], ky = a.t.ky[iy], kz = kz_of(a.g, iz);
     const float k2 = kx * kx + ky * ky + kz * kz;
     if constexpr (MODE == ZM_ABS) {
         if (k2 <= 0.0f) return make_float2(0.0f, 0.0f);
@@ -364,7 +395,6 @@ struct ZCtx {
     uint32_t lane;           // byte offset of (z = t, column b) from the tile
     ColLds lds;
     const float2 *tws;
-    const float *kzl;
     const float2 *dzl;
 };
 
@@ -416,7 +446,7 @@ __device__ __forceinline__ void z_op(const ZArgs &a, const ZCtx &c, int o, float
     for (int m = 0; m < E; ++m)
         if (m < cmid)
             v[m] = c_mul(v[m], c_scale(z_operator<OPMODE>(a, o, c.ix, c.iyk, Eng::out_index(a.pf, t, m),
-                                                          c.kzl, c.dzl), scale));
+                                                          c.dzl), scale));
     if (c.pairing) {
         // (kz, -kz) pairs of the double row, one pair per iteration and thread,
         // updated in place in LDS (a pair is read and written by one thread)
@@ -430,13 +460,13 @@ __device__ __forceinline__ void z_op(const ZArgs &a, const ZCtx &c, int o, float
                 const float2 s1 = c_add(c1, c_conj(c2)), d1 = c_sub(c1, c_conj(c2));
                 const float2 A1 = c_scale(s1, 0.5f * scale);
                 const float2 B1 = make_float2(0.5f * scale * d1.y, -0.5f * scale * d1.x);
-                const float2 ya = c_mul(A1, z_operator<OPMODE>(a, o, 0, iy, iz, c.kzl, c.dzl));
-                const float2 yb = c_mul(B1, z_operator<OPMODE>(a, o, M, iy, iz, c.kzl, c.dzl));
+                const float2 ya = c_mul(A1, z_operator<OPMODE>(a, o, 0, iy, iz, c.dzl));
+                const float2 yb = c_mul(B1, z_operator<OPMODE>(a, o, M, iy, iz, c.dzl));
                 lds.st(iz, make_float2(ya.x - yb.y, ya.y + yb.x));          // ya + i yb
                 if (jz != iz) {
                     // A(-kz) = conj A(kz), B(-kz) = conj B(kz)
-                    const float2 za = c_mul(c_conj(A1), z_operator<OPMODE>(a, o, 0, iy, jz, c.kzl, c.dzl));
-                    const float2 zb = c_mul(c_conj(B1), z_operator<OPMODE>(a, o, M, iy, jz, c.kzl, c.dzl));
+                    const float2 za = c_mul(c_conj(A1), z_operator<OPMODE>(a, o, 0, iy, jz, c.dzl));
+                    const float2 zb = c_mul(c_conj(B1), z_operator<OPMODE>(a, o, M, iy, jz, c.dzl));
                     lds.st(jz, make_float2(za.x - zb.y, za.y + zb.x));
                 }
             }
@@ -459,14 +489,17 @@ __device__ __forceinline__ void z_fwd_op(const ZArgs &a, const ZCtx &c, int o, f
     z_op<Eng, OPMODE>(a, c, o, scale, v);
 }
 
-template <class Eng, int MODE, int MAXT = 512>
+// SPLIT (gradient only): one block per output, as for the generic engines,
+// instead of one block that keeps the forward spectrum for all three (the
+// kept spectrum holds 32 more registers, too many for two 512-thread blocks
+// per CU on long columns)
+template <class Eng, int MODE, int MAXT = 512, bool SPLIT = false>
 __global__ void __launch_bounds__(MAXT) kw_zfused(ZArgs a) {
     constexpr int E = Eng::E;
-    // LDS: nz twiddles, nz z factors, nz wavenumbers kz, then the column tile
+    // LDS: nz twiddles, nz z factors, then the column tile
     extern __shared__ float2 lds_all[];
     float2 *const tws = lds_all;
     float2 *const dzl = lds_all + a.g.nz;
-    float *const kzl = reinterpret_cast<float *>(lds_all + 2 * a.g.nz);
     float2 *const sh = lds_all + zpass_table_slots(a.g.nz);
     const int tid = threadIdx.x;
     const int b = tid % a.tb, t = tid / a.tb;
@@ -480,22 +513,16 @@ __global__ void __launch_bounds__(MAXT) kw_zfused(ZArgs a) {
     // ALU work, and this saves two of the six transforms of a tile).  The
     // generic engines' register arrays are sized for their largest radix and
     // a kept spectrum would cost them two wavefronts per SIMD, so their
-    // gradient keeps one block per output, in a 1D grid ordered so that the
-    // three blocks of a tile land on the same XCD (workgroups go round-robin
-    // over the 8 XCDs) one after another: the second and third reads of the
-    // tile hit that XCD's L2.  The merged absorption (ABSM) block transforms
-    // both inputs and writes one output.
-    constexpr bool fused_grad = MODE == ZM_GRAD && Eng::fixed;
+    // gradient keeps one block per output (so does a SPLIT instantiation of a
+    // fixed engine), and the three blocks of a tile come one after another on
+    // one XCD (xcd_order): the second and third reads of the tile hit that
+    // XCD's L2.  The merged absorption (ABSM) block transforms both inputs and
+    // writes one output.
+    constexpr bool fused_grad = MODE == ZM_GRAD && Eng::fixed && !SPLIT;
+    constexpr int R = (MODE == ZM_GRAD && !fused_grad) ? 3 : 1;
     int blk, o;
-    if constexpr (MODE == ZM_GRAD && !Eng::fixed) {
-        const int B = blockIdx.x, q = B >> 3;
-        blk = (q / 3) * 8 + (B & 7);
-        o = q % 3;
-        if (blk >= a.ntiles * a.g.ny) return;          // whole block: padding of the grid
-    } else {
-        blk = blockIdx.x;
-        o = (MODE == ZM_GRAD) ? 0 : blockIdx.y;
-    }
+    if (!xcd_order(blockIdx.x, line_group(a.tb), R, a.ntiles * a.g.ny, blk, o)) return;
+    if constexpr (MODE != ZM_GRAD) o = blockIdx.y;
     const int f = (MODE == ZM_GRAD) ? 0 : o;
 
     ZCtx c;
@@ -511,7 +538,6 @@ __global__ void __launch_bounds__(MAXT) kw_zfused(ZArgs a) {
     c.lane = (uint32_t)((size_t)t * c.stride + b) * 8u;
     c.lds = ColLds{sh, a.tb, b};
     c.tws = tws;
-    c.kzl = kzl;
     c.dzl = dzl;
     // column 0 of this row (see col0_type): A rows take kx = 0, B rows the
     // Nyquist kx, and the double rows are split with their kz <-> -kz partner
@@ -528,7 +554,6 @@ __global__ void __launch_bounds__(MAXT) kw_zfused(ZArgs a) {
     stage_table(tws, a.t.tw_z, a.g.nz);
     if constexpr (MODE != ZM_ABS && MODE != ZM_ABSM)
         stage_table(dzl, (MODE == ZM_GRAD || MODE == ZM_GRADT) ? a.t.dpz : a.t.dmz, a.g.nz);
-    for (int i = threadIdx.x; i < a.g.nz; i += blockDim.x) kzl[i] = a.t.kz[i];
     __syncthreads();
     if constexpr (fused_grad) {
         Eng::template run<false>(a.pf, c.tws, t, c.lds, v);
@@ -1224,10 +1249,13 @@ __global__ void __launch_bounds__(512) kw_xden3(XArgs a) {
 // pass of a medium with scalar ta, tb) instead of a and b.
 // Asked to fit six wavefronts per SIMD (80 registers; a few bytes spill):
 // measured faster than five without spills.
+// The sensor and pressure-source lines alias the FFT row buffers (nx floats a
+// row fit in a buffer of row_pitch(M) complex values): they are used only
+// between the inverse transforms and the forward one, behind block barriers.
 template <class Eng, bool SENS, bool MERGED>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6))) kw_xeos(XArgs a) {
     KW_XPROLOGUE
-    float *line = reinterpret_cast<float *>(sh + (size_t)a.tb * row_pitch(M));
+    float *line = reinterpret_cast<float *>(sh);
     float2 va[E], v[E];
     if constexpr (!MERGED)
         row_c2r<Eng>(a, a.Sin[0], b, ok, t, lds, va, tws, tws + M);

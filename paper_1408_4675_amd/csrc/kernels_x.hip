@@ -119,13 +119,14 @@ hipError_t launch_xeos(hipStream_t s, const GridDev &g, const LaunchCfg &c, cons
     a.Sin[1] = Sin[1];
     a.rho_total = const_cast<float *>(rho_total);
     a.Sout[0] = Sout;
-    // the per-row line is only needed to pick mask sensor points out of a row
+    // mask sensor points and pressure-source values are picked out of a row
+    // through a line that aliases the row's FFT buffer (no LDS of its own)
     const bool mask = sen.row_ptr != nullptr && !sen.all_points;
     const bool psrc = src.row_ptr != nullptr && src.kind == KW_SOURCE_PRESSURE;
     const bool extra = sen.p_min != nullptr || sen.harm != nullptr || psrc;
     dim3 grid((g.rows + c.tb_x - 1) / c.tb_x);
     dim3 block(c.tb_x * c.px.L);
-    const size_t lds = x_lds(g, c, mask || psrc);
+    const size_t lds = x_lds(g, c, false);
     const int variant = (mask || extra ? 1 : 0) | (merged ? 2 : 0);
     switch (variant) {
     case 0: KW_ENGINE_SWITCH(c.eng_x, hipLaunchKernelGGL((kw_xeos<Eng, false, false>), grid, block, lds, s, a)); break;

@@ -21,7 +21,10 @@ hipError_t launch_ypass(hipStream_t s, const GridDev &g, const LaunchCfg &c, con
         a.n_harm = sen->n_harm;
         a.harm_wdt = sen->harm_wdt;
     }
-    dim3 grid((g.M + a.tb - 1) / a.tb, g.nz, nfields);
+    a.ntiles = (g.M + a.tb - 1) / a.tb;
+    a.nz = g.nz;
+    // one workgroup per (tile, z plane) in XCD-aware order (xcd_order), per field
+    dim3 grid(xcd_grid(a.ntiles * g.nz, line_group(a.tb), 1), 1, nfields);
     dim3 block(a.tb * a.plan.L);
     size_t lds = col_lds_bytes(g.ny, a.tb);
     if (block.x > 512) {
@@ -71,25 +74,31 @@ hipError_t launch_zfused(hipStream_t s, const GridDev &g, const LaunchCfg &c, co
     a.sa = sa;
     a.sb = sb;
     const bool fixed_z = eng_fixed(c.eng_z);
-    if ((mode == ZM_ABSM || (mode == ZM_GRAD && fixed_z)) && a.tb * c.pz.L > 512 && a.tb > 1) {
-        // the merged absorption and the gradient hold two spectra per thread:
-        // they do not fit the registers of a 1024-thread block, so they run
-        // half-width tiles
+    if (mode == ZM_ABSM && a.tb * c.pz.L > 512 && a.tb > 1) {
+        // the merged absorption holds two spectra per thread: they do not fit
+        // the registers of a 1024-thread block, so it runs half-width tiles
         a.tb /= 2;
         a.ntiles = (g.M + a.tb - 1) / a.tb;
     }
-    // one block per tile and output (with the fixed engines the gradient's
-    // block writes all three; with the generic ones its blocks come in a 1D
-    // grid in XCD-aware order, padded to whole groups of 8 tiles)
+    // The gradient of a fixed engine keeps the forward spectrum for its three
+    // outputs in one block, except on long columns (blocks of 512 threads or
+    // more), where the kept spectrum would leave one block per CU: there it
+    // runs one block per output (split), like the generic engines.
+    const bool split = mode == ZM_GRAD && (!fixed_z || a.tb * c.pz.L >= 512);
+    // one block per tile and output, in XCD-aware order (xcd_order): the
+    // gradient's blocks (one, or three when split) in a 1D grid, the other
+    // modes' outputs along blockIdx.y
     const int nblk = a.ntiles * g.ny;
+    const int G = line_group(a.tb);
     dim3 grid;
-    if (mode == ZM_GRAD) grid = fixed_z ? dim3(nblk, 1) : dim3((nblk + 7) / 8 * 8 * 3, 1);
-    else grid = dim3(nblk, z_outputs(mode));
+    if (mode == ZM_GRAD) grid = dim3(xcd_grid(nblk, G, split ? 3 : 1), 1);
+    else grid = dim3(xcd_grid(nblk, G, 1), z_outputs(mode));
     dim3 block(a.tb * c.pz.L);
     size_t lds = zcol_lds_bytes(g.nz, a.tb);
 #define KW_ZMODES(ENGT, MAXT)                                                                  \
     do {                                                                                       \
-        if (mode == ZM_GRAD) hipLaunchKernelGGL((kw_zfused<ENGT, ZM_GRAD, MAXT>), grid, block, lds, s, a);   \
+        if (mode == ZM_GRAD && split) hipLaunchKernelGGL((kw_zfused<ENGT, ZM_GRAD, MAXT, true>), grid, block, lds, s, a); \
+        else if (mode == ZM_GRAD) hipLaunchKernelGGL((kw_zfused<ENGT, ZM_GRAD, MAXT>), grid, block, lds, s, a);   \
         else if (mode == ZM_DIV) hipLaunchKernelGGL((kw_zfused<ENGT, ZM_DIV, MAXT>), grid, block, lds, s, a); \
         else if (mode == ZM_ABS) hipLaunchKernelGGL((kw_zfused<ENGT, ZM_ABS, MAXT>), grid, block, lds, s, a); \
         else if (mode == ZM_DIVT) hipLaunchKernelGGL((kw_zfused<ENGT, ZM_DIVT, MAXT>), grid, block, lds, s, a); \

@@ -48,6 +48,7 @@ struct GridDev {
     float dt;
     float y_tau;             // (y - 2) / 2, exponent of k^2 for k^(y-2)
     float y_eta;             // (y - 1) / 2
+    float dkz;               // 2 pi / (nz dz): kz of FFT index m is m dkz (Eq. (5))
 };
 
 // 1D tables (device), float32 copies of float64 host values.
@@ -173,8 +174,8 @@ inline size_t x_lds_bytes(int M, int nx, int tb, bool line) {
     return (size_t)2 * M * 8 + (size_t)tb * rp * 8 + (line ? (size_t)tb * nx * 4 : 0);
 }
 inline size_t col_lds_bytes(int n, int tb) { return (size_t)n * 8 + (size_t)tb * n * 8; }
-// the z pass keeps three tables of nz entries (twiddles, z factors, kz) before its tile
-__host__ __device__ inline int zpass_table_slots(int nz) { return 2 * nz + (nz + 1) / 2; }
+// the z pass keeps two tables of nz entries (twiddles, z factors) before its tile
+__host__ __device__ inline int zpass_table_slots(int nz) { return 2 * nz; }
 inline size_t zcol_lds_bytes(int n, int tb) {
     return (size_t)zpass_table_slots(n) * 8 + (size_t)tb * n * 8;
 }
@@ -208,6 +209,10 @@ struct AdjDev {
     const int *src_elem;
     const float *src_coef;
     float *corr;             // [3][n_src] source correction of the divergence adjoint
+    double *share;           // [n_src] share of each source point in dJ/ds_e(n)
+    const int *elem_ptr;     // [n_elem + 1] CSR of the points of each element
+    const int *elem_pts;     // point numbers (k) of the elements, element by element
+    double *partials;        // per-block partial sums of the objective
 };
 
 // launchers (kernels_yz.hip, kernels_x.hip, kernels_util.hip, kernels_adj.hip) ------
@@ -247,8 +252,10 @@ hipError_t launch_adj_src_fix(hipStream_t s, const AdjDev &a, const Medium &m);
 hipError_t launch_adj_vel(hipStream_t s, const GridDev &g, const Tables &t, const Medium &m,
                           const AdjDev &a);
 hipError_t launch_adj_sum(hipStream_t s, const GridDev &g, const AdjDev &a);
+// objective J into *out through per-block partials (adj_objective_blocks of them)
+int adj_objective_blocks(const GridDev &g);
 hipError_t launch_adj_objective(hipStream_t s, const GridDev &g, const float *w,
-                                const float *sum2, double *out);
+                                const float *sum2, double *partials, double *out);
 hipError_t launch_fill(hipStream_t s, float *p, size_t n, float v);
 hipError_t launch_scale(hipStream_t s, const float *src, float *dst, size_t n, float scale);
 hipError_t launch_fill_int(hipStream_t s, int *p, size_t n, int v);

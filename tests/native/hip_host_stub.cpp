@@ -6,6 +6,7 @@
 // fail with hipErrorLaunchFailure (error propagation tests).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cstring>
 
@@ -95,8 +96,11 @@ hipError_t launch_adj_src_fix(hipStream_t, const AdjDev &, const Medium &) { ret
 hipError_t launch_adj_vel(hipStream_t, const GridDev &, const Tables &, const Medium &,
                           const AdjDev &) { return launch_status(); }
 hipError_t launch_adj_sum(hipStream_t, const GridDev &, const AdjDev &) { return launch_status(); }
+int adj_objective_blocks(const GridDev &g) {
+    return (int)std::min<size_t>(((size_t)g.nx * g.rows + 255) / 256, 65535u * 8u);
+}
 hipError_t launch_adj_objective(hipStream_t, const GridDev &, const float *, const float *,
-                                double *) { return launch_status(); }
+                                double *, double *) { return launch_status(); }
 hipError_t launch_scale(hipStream_t, const float *, float *, size_t, float) { return launch_status(); }
 hipError_t launch_finalize(hipStream_t, const float *, float *, size_t, float, int, Coef, Coef,
                            const int *) { return launch_status(); }

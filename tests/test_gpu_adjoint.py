@@ -84,3 +84,17 @@ def test_adjoint_rejects_wrong_state(kw):
     adj.step(2)
     adj.close()
     sim.close()
+
+
+def test_adjoint_is_bitwise_repeatable(kw):
+    """The per-element sums of dJ/ds_e(n) and the objective are reduced in a
+    fixed order (no floating-point atomics): two runs give identical bits."""
+    from paper_1408_4675_amd.adjoint import focus_gradient
+    scen, w = _case(True, True, True, steps=30, elements=5)
+    print("\n[case] adjoint repeatability", flush=True)
+    a = focus_gradient(scen, w, checkpoint_every=10)
+    b = focus_gradient(scen, w, checkpoint_every=10)
+    assert a["J"] == b["J"]
+    assert np.array_equal(a["source_gradient"], b["source_gradient"])
+    assert np.array_equal(a["grad_amp"], b["grad_amp"])
+    assert np.array_equal(a["grad_phase"], b["grad_phase"])
