@@ -212,6 +212,24 @@ int kw_create_prepared(const kw_plan *plan, void *dev_workspace, size_t ws_bytes
                        kw_sim **out);
 int kw_plan_destroy(kw_plan *plan);
 
+/* For callers that cannot allocate device memory beyond their inputs and
+ * outputs (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): kw_create with the six spectral scratch arrays of the
+ * step (packed half spectra, dead between steps) taken from one static array
+ * of the library instead of the workspace.  The workspace then needs
+ *     kw_workspace_size(...) - 6 S bytes,   S = 256 * ceil(4 * nx * ny * nz / 256),
+ * and the six arrays must fit the static array of 96 MiB (6 S <= 100663296
+ * bytes: grids up to about 4.19 million points, 160^3 for instance); larger
+ * grids fail with KW_EUNSUPPORTED before any device work.  Neither this call
+ * nor any later call on the simulation allocates device memory.  Every
+ * simulation made this way on one GPU shares that GPU's array, which keeps
+ * the last call's contents (nothing needs clearing: a step writes the arrays
+ * before reading them): their steps, gathers and reverse steps must not
+ * overlap in time, or they race.  Other statuses as kw_create. */
+int kw_create_static(const kw_grid *grid, const kw_medium *medium, const kw_source *source,
+                     const kw_sensor *sensor, void *dev_workspace, size_t ws_bytes, void *stream,
+                     kw_sim **out);
+
 /* Enqueue n >= 0 time steps on the simulation's stream and return. */
 int kw_step(kw_sim *sim, int32_t n);
 

@@ -46,7 +46,7 @@ KW_FIELD_RHOZ = 7
 
 # every symbol include/kw.h declares
 EXPORTS = ("kw_workspace_size", "kw_create", "kw_prepare", "kw_plan_workspace_size",
-           "kw_create_prepared", "kw_plan_destroy", "kw_step", "kw_gather", "kw_gather_bytes",
+           "kw_create_prepared", "kw_plan_destroy", "kw_create_static", "kw_step", "kw_gather", "kw_gather_bytes",
            "kw_set_field", "kw_gather_field", "kw_profile", "kw_stats", "kw_set_graph",
            "kw_set_plan", "kw_state_bytes", "kw_save", "kw_load", "kw_adjoint_workspace_size",
            "kw_adjoint_create", "kw_adjoint_objective", "kw_adjoint_step", "kw_adjoint_source_gradient",
@@ -132,6 +132,9 @@ def _load(path):
     lib.kw_create_prepared.restype = C.c_int
     lib.kw_create_prepared.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p,
                                        P(C.c_void_p)]
+    lib.kw_create_static.restype = C.c_int
+    lib.kw_create_static.argtypes = [P(KwGrid), P(KwMedium), P(KwSource), P(KwSensor), C.c_void_p,
+                                     C.c_size_t, C.c_void_p, P(C.c_void_p)]
     lib.kw_plan_destroy.restype = C.c_int
     lib.kw_plan_destroy.argtypes = [C.c_void_p]
     lib.kw_step.restype = C.c_int

@@ -35,7 +35,8 @@ def _run(cmd):
     return r.stdout
 
 
-HIP_SOURCES = ("kernels_yz.hip", "kernels_x.hip", "kernels_util.hip", "kernels_adj.hip")
+HIP_SOURCES = ("kernels_yz.hip", "kernels_x.hip", "kernels_util.hip", "kernels_adj.hip",
+               "static_scratch.hip")
 
 
 def build(verbose: bool = False, extra_flags=()) -> str:

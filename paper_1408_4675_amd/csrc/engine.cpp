@@ -443,6 +443,7 @@ struct kw_sim {
     uint32_t flags;
     hipStream_t stream;
     char *ws;
+    size_t ws_used = 0;                // bytes of the workspace in use
     Layout L;
     Counts cnt;
     GridDev g;
@@ -1066,23 +1067,44 @@ void bind(kw_sim *s, const MediumShape &ms) {
 
 // Device part of set-up: bind a prepared plan to a workspace and a stream,
 // choose the launch shapes, upload the tables and maps, zero the state.
+// With `static_spectra` the six spectral scratch arrays S1..S6 (the last
+// regions of the layout) come from the library's static scratch array and the
+// workspace ends where S1 would start.
 int create_prepared(const kw_plan *P, void *dev_workspace, size_t ws_bytes, void *stream,
-                    kw_sim **out) {
+                    kw_sim **out, bool static_spectra = false) {
     if (!out) return fail(KW_EINVAL, "out must not be NULL");
     *out = nullptr;
     if (!P) return fail(KW_EINVAL, "plan must not be NULL");
     const Layout &L = P->proto.L;
+    const size_t need = static_spectra ? L.S[1] : L.total;
     if (!dev_workspace) return fail(KW_EINVAL, "workspace must not be NULL");
     if ((reinterpret_cast<uintptr_t>(dev_workspace) % kAlign) != 0)
         return fail(KW_EINVAL, "workspace must be %zu-byte aligned", kAlign);
-    if (ws_bytes < L.total)
-        return fail(KW_ENOMEM, "workspace has %zu bytes, %zu needed", ws_bytes, L.total);
+    if (ws_bytes < need)
+        return fail(KW_ENOMEM, "workspace has %zu bytes, %zu needed", ws_bytes, need);
+    char *spectra = nullptr;
+    if (static_spectra) {
+        void *p = nullptr;
+        size_t cap = 0;
+        const hipError_t e = static_scratch(&p, &cap);
+        if (e != hipSuccess)
+            return fail(KW_EDEVICE, "static scratch address: %s", hipGetErrorString(e));
+        if (L.total - L.S[1] > cap)
+            return fail(KW_EUNSUPPORTED,
+                        "the six spectral scratch arrays need %zu bytes, the static scratch "
+                        "array holds %zu", L.total - L.S[1], cap);
+        spectra = reinterpret_cast<char *>(p);
+    }
     kw_sim *s = new (std::nothrow) kw_sim(P->proto);
     if (!s) return fail(KW_EINVAL, "out of host memory");
     s->stream = reinterpret_cast<hipStream_t>(stream);
     s->ws = reinterpret_cast<char *>(dev_workspace);
+    s->ws_used = need;
     if (s->stream == nullptr) s->graph_steps = 0;   // the legacy stream cannot be captured
     bind(s, P->ms);
+    if (spectra)
+        for (int i = 1; i < 7; ++i)
+            s->buf.S[i] = reinterpret_cast<float2 *>(spectra + (L.S[i] - L.S[1]));
     const Counts &cnt = s->cnt;
     const size_t N = (size_t)s->grid.nx * s->grid.ny * s->grid.nz;
     SensorDev &se = s->sen;
@@ -1179,6 +1201,17 @@ size_t kw_plan_workspace_size(const kw_plan *plan) { return plan ? plan->proto.L
 int kw_create_prepared(const kw_plan *plan, void *dev_workspace, size_t ws_bytes, void *stream,
                        kw_sim **out) {
     return create_prepared(plan, dev_workspace, ws_bytes, stream, out);
+}
+
+int kw_create_static(const kw_grid *grid, const kw_medium *medium, const kw_source *source,
+                     const kw_sensor *sensor, void *dev_workspace, size_t ws_bytes, void *stream,
+                     kw_sim **out) {
+    if (!out) return fail(KW_EINVAL, "out must not be NULL");
+    *out = nullptr;
+    kw_plan P{};
+    const int rc = prepare(grid, medium, source, sensor, &P);
+    if (rc != KW_OK) return rc;
+    return create_prepared(&P, dev_workspace, ws_bytes, stream, out, true);
 }
 
 int kw_plan_destroy(kw_plan *plan) {
@@ -1401,7 +1434,7 @@ int kw_stats(kw_sim *s, kw_stats_t *out) {
     out->nonfinite_step = flag == INT_MAX ? -1 : flag;
     out->dt = s->dt;
     out->c_ref = s->c_ref;
-    out->workspace_bytes = (int64_t)s->L.total;
+    out->workspace_bytes = (int64_t)s->ws_used;
     out->fft_forward_per_step = s->med.absorbing ? 6 : 4;
     out->fft_inverse_per_step = s->med.absorbing ? (s->merged_abs ? 7 : 8) : 6;
     out->kernels_per_step = s->kernels_per_step;

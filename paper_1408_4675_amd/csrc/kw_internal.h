@@ -256,6 +256,10 @@ hipError_t launch_adj_sum(hipStream_t s, const GridDev &g, const AdjDev &a);
 int adj_objective_blocks(const GridDev &g);
 hipError_t launch_adj_objective(hipStream_t s, const GridDev &g, const float *w,
                                 const float *sum2, double *partials, double *out);
+// the static scratch array of kw_create_static (static_scratch.hip): its
+// device address on the current device and its size
+constexpr size_t kStaticScratchBytes = (size_t)96 << 20;
+hipError_t static_scratch(void **out, size_t *bytes);
 hipError_t launch_fill(hipStream_t s, float *p, size_t n, float v);
 hipError_t launch_scale(hipStream_t s, const float *src, float *dst, size_t n, float scale);
 hipError_t launch_fill_int(hipStream_t s, int *p, size_t n, int v);

@@ -154,22 +154,35 @@ def _own_stream(device: torch.device):
     return handle.value, torch.cuda.ExternalStream(handle.value, device=device)
 
 
+def static_workspace_size(sc: Scenario) -> int:
+    """Workspace bytes of a simulation whose six spectral scratch arrays live in
+    the library's static array (kw_create_static)."""
+    g = sc.grid
+    spectrum = 256 * ((4 * g.nx * g.ny * g.nz + 255) // 256)
+    return workspace_size(sc) - 6 * spectrum
+
+
 class Simulation:
     """One simulation on the GPU.  It runs on a HIP stream of its own (or on
-    `stream` when one is given); the device workspace is a torch tensor."""
+    `stream` when one is given); the device workspace is a torch tensor.  With
+    static_scratch the spectral scratch arrays come from the library's static
+    array (kw_create_static): a smaller workspace, and simulations made so on
+    one GPU must not run at the same time."""
 
     def __init__(self, sc: Scenario, device: str = "cuda", stream: Optional[torch.cuda.Stream] = None,
                  graph_steps: Optional[int] = None, tune: bool = True,
-                 prepared: Optional[Prepared] = None):
+                 prepared: Optional[Prepared] = None, static_scratch: bool = False):
         self.lib = A.load()
         self.scenario = sc
         self.device = torch.device(device)
         self.handle = None
         self._own = None
-        own_prep = prepared is None
+        if static_scratch and prepared is not None:
+            raise ValueError("static_scratch builds its own set-up (no prepared plan)")
+        own_prep = prepared is None and not static_scratch
         prep = Prepared(sc) if own_prep else prepared
         try:
-            nbytes = prep.workspace_bytes
+            nbytes = static_workspace_size(sc) if static_scratch else prep.workspace_bytes
             self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
             if stream is None:
                 self._own, self.stream = _own_stream(self.device)
@@ -180,9 +193,18 @@ class Simulation:
             # simulation's stream before the workspace is released
             self.stream.wait_stream(torch.cuda.current_stream(self.device))
             handle = C.c_void_p()
-            A.check(self.lib.kw_create_prepared(prep.handle, C.c_void_p(self.workspace.data_ptr()),
-                                                C.c_size_t(nbytes), C.c_void_p(self.stream.cuda_stream),
-                                                C.byref(handle)))
+            if static_scratch:
+                m = _Marshalled(sc)
+                A.check(self.lib.kw_create_static(*m.args(), C.c_void_p(self.workspace.data_ptr()),
+                                                  C.c_size_t(nbytes),
+                                                  C.c_void_p(self.stream.cuda_stream),
+                                                  C.byref(handle)))
+            else:
+                A.check(self.lib.kw_create_prepared(prep.handle,
+                                                    C.c_void_p(self.workspace.data_ptr()),
+                                                    C.c_size_t(nbytes),
+                                                    C.c_void_p(self.stream.cuda_stream),
+                                                    C.byref(handle)))
             self.handle = handle
         except Exception:
             self.close()

@@ -227,6 +227,32 @@ int run_errors() {
     plan = reinterpret_cast<kw_plan *>(0x1);
     EXPECT(kw_prepare(&bad, &in.medium, &in.source, &in.sensor, &plan) == KW_EUNSUPPORTED && !plan,
            "prepare of an odd nx");
+    // kw_create_static: the workspace ends before the six spectral arrays,
+    // which must fit the static array (1 MiB in the host stand-in)
+    {
+        Inputs sm;
+        make_inputs(1, sm);
+        sm.grid.nx = sm.grid.ny = sm.grid.nz = 16;
+        for (int a = 0; a < 3; ++a) sm.grid.pml_size[a] = 2;
+        sm.source.n_points = 0;
+        const size_t full = kw_workspace_size(&sm.grid, &sm.medium, &sm.source, &sm.sensor);
+        const size_t spec = (4 * 16 * 16 * 16 + 255) / 256 * 256;
+        Buffer w2(full - 6 * spec);
+        kw_sim *st = nullptr;
+        EXPECT(kw_create_static(&sm.grid, &sm.medium, &sm.source, &sm.sensor, w2.p, w2.n - 1,
+                                nullptr, &st) == KW_ENOMEM && !st, "static: one byte short");
+        rc = kw_create_static(&sm.grid, &sm.medium, &sm.source, &sm.sensor, w2.p, w2.n, nullptr, &st);
+        EXPECT(rc == KW_OK && st, "static create returned %d: %s", rc, kw_last_error());
+        kw_stats_t stt;
+        EXPECT(kw_stats(st, &stt) == KW_OK && (size_t)stt.workspace_bytes == full - 6 * spec,
+               "static workspace bytes");
+        EXPECT(kw_destroy(st) == KW_OK, "static destroy");
+        // 48 x 40 x 36: six spectra of 276480 bytes exceed the static array
+        Buffer w3(need);
+        st = nullptr;
+        rc = kw_create_static(&in.grid, &in.medium, &in.source, &in.sensor, w3.p, w3.n, nullptr, &st);
+        EXPECT(rc == KW_EUNSUPPORTED && !st, "static create of a grid too large returned %d", rc);
+    }
     std::printf("error paths ok\n");
     return 0;
 }

@@ -55,6 +55,14 @@ hipError_t hipEventElapsedTime(float *ms, hipEvent_t, hipEvent_t) { *ms = 0.0f; 
 
 namespace kw {
 
+// the static scratch array stands in as host memory here
+hipError_t static_scratch(void **out, size_t *bytes) {
+    alignas(256) static unsigned char host_scratch[1 << 20];
+    *out = host_scratch;
+    *bytes = sizeof host_scratch;
+    return launch_status();
+}
+
 hipError_t launch_fill(hipStream_t, float *p, size_t n, float v) {
     for (size_t i = 0; i < n; ++i) p[i] = v;
     return launch_status();
