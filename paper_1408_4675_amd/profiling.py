@@ -59,7 +59,7 @@ def kernel_class(name: str) -> Optional[str]:
     m = re.search(r"kw_ypass<.*?, (true|false)(, \d+)?>", name)
     if m:
         return "ypass_inv" if m.group(1) == "true" else "ypass_fwd"
-    m = re.search(r"kw_zfused<.*?>, (\d)(, \d+)?>", name)
+    m = re.search(r"kw_zfused<.*?>, (\d)(, \d+)?(, (true|false))?>", name)
     if m:
         return {"0": "zfused_grad", "1": "zfused_div", "2": "zfused_abs",
                 "3": "zfused_divt", "4": "zfused_gradt",
