@@ -473,6 +473,8 @@ struct kw_sim {
     std::vector<hipEvent_t> pool;
     size_t max_lds = 64 * 1024;        // LDS bytes a block may use on this device
     bool merged_abs = false;           // absorption terms merged (scalar c0^2 tau, c0^2 eta)
+    bool rho0_sum_in_z = false;        // absorbing with a constant rho0: the divergence
+                                       // pass forms the spectrum of rho0 sum du
     // host copy of the source set-up (for the reverse-mode step)
     std::vector<int> src_flat, src_elem;
     std::vector<float> src_coef;
@@ -577,6 +579,44 @@ hipError_t enqueue_step(kw_sim *s) {
     KW_L(KC_XVEL, 12 + (ms.het[MED_DTRX] ? 3 : 0),
          launch_xvel(st, g, c, t, s->med, s123, s->buf.u, s->src, s->sen, s->counters));
     KW_L(KC_YFWD, 6, launch_ypass(st, g, c, t, s123, 3, false, nullptr, nullptr));
+    if (s->rho0_sum_in_z) {
+        // Constant rho0: the tau term of Eq. (8) transforms rho0 sum du, whose
+        // (kx, ky) spectrum is rho0 nx ny times the sum of the three
+        // divergence outputs of the z pass (S4..S6, before their y inverse
+        // transform).  The y inverse transform writes them to S1..S3 instead
+        // of in place, the density pass transforms rho alone (into S0), and
+        // the absorption pass sums S4 + S5 + S6 as it loads its tau input: one
+        // forward x and y transform less, and no write of a spectrum.
+        const float r0nxny = (float)((double)s->med.rho0.scalar * g.nx * g.ny);
+        KW_L(KC_ZDIV, 6, launch_zfused(st, g, c, t, ZM_DIV, s123, s456));
+        KW_L(KC_YINV, 6, launch_ypass(st, g, c, t, s456, 3, true, nullptr, nullptr, nullptr, s123));
+        float2 *rho_out[2] = {S[0], S[0]};
+        KW_L(KC_XDEN, 11, launch_xden(st, g, c, t, s->med, s->src, s->sen, s->counters, s123,
+                                      s->buf.rho, s->buf.rho_total, rho_out, true));
+        KW_L(KC_YFWD, 2, launch_ypass(st, g, c, t, s0, 1, false, nullptr, nullptr));
+        float2 *in[2] = {S[4], S[0]};
+        float2 *add0[2] = {S[5], S[6]};
+        const double med_units = (ms.het[MED_C0SQ] ? 1 : 0) + (ms.het[MED_NL] ? 1 : 0) +
+                                 (ms.het[MED_TA] ? 2 : 0);
+        if (s->merged_abs) {
+            float2 *s1[1] = {S[1]};
+            KW_L(KC_ZABS, 5, launch_zfused(st, g, c, t, ZM_ABSM, in, s1, s->med.ta.scalar * r0nxny,
+                                           s->med.tb.scalar, add0));
+            KW_L(KC_YINV, 2, launch_ypass(st, g, c, t, s1, 1, true, nullptr, nullptr));
+            KW_L(KC_XEOS, 3 + med_units + sens_units,
+                 launch_xeos(st, g, c, t, s->med, s->src, s->sen, s->counters, s1,
+                             s->buf.rho_total, S[0], true));
+        } else {
+            float2 *s12[2] = {S[1], S[2]};
+            KW_L(KC_ZABS, 6, launch_zfused(st, g, c, t, ZM_ABS, in, s12, r0nxny, 1.0f, add0));
+            KW_L(KC_YINV, 4, launch_ypass(st, g, c, t, s12, 2, true, nullptr, nullptr));
+            KW_L(KC_XEOS, 4 + med_units + sens_units,
+                 launch_xeos(st, g, c, t, s->med, s->src, s->sen, s->counters, s12,
+                             s->buf.rho_total, S[0]));
+        }
+        s->kernels_per_step = nk;
+        return hipSuccess;
+    }
     KW_L(KC_ZDIV, 6, launch_zfused(st, g, c, t, ZM_DIV, s123, s456));
     KW_L(KC_YINV, 6, launch_ypass(st, g, c, t, s456, 3, true, nullptr, nullptr));
     if (absorbing) {
@@ -892,6 +932,7 @@ int prepare(const kw_grid *grid, const kw_medium *medium, const kw_source *sourc
     md.nonlinear = nonlinear;
     md.absorbing = absorbing;
     s->merged_abs = absorbing && !ms.het[MED_TA];
+    s->rho0_sum_in_z = absorbing && !ms.het[MED_RHO0];
     {
         auto fill_map = [&](int which, auto fn, Coef &dst) {
             if (ms.het[which]) {
@@ -1435,7 +1476,7 @@ int kw_stats(kw_sim *s, kw_stats_t *out) {
     out->dt = s->dt;
     out->c_ref = s->c_ref;
     out->workspace_bytes = (int64_t)s->ws_used;
-    out->fft_forward_per_step = s->med.absorbing ? 6 : 4;
+    out->fft_forward_per_step = s->med.absorbing ? (s->rho0_sum_in_z ? 5 : 6) : 4;
     out->fft_inverse_per_step = s->med.absorbing ? (s->merged_abs ? 7 : 8) : 6;
     out->kernels_per_step = s->kernels_per_step;
     out->n_classes = KC_COUNT;

@@ -205,6 +205,7 @@ __device__ __forceinline__ float drive_at(const SourceDev &src, int e, int n) {
 // ---------------------------------------------------------------------------
 struct YArgs {
     float2 *f[3];
+    float2 *o[3];            // destinations (the same as f for an in-place pass)
     int M, ny;
     FftPlan plan;            // forward plan, or the reversed plan for the inverse
     const float2 *tw;
@@ -239,19 +240,23 @@ __global__ void __launch_bounds__(MAXT) kw_ypass(YArgs a) {
     const bool ok = col < a.M;
     // element (row t + m step, column col) of this block's tile: uniform base
     // base + m step M, lane offset (t M + b) elements
-    float2 *const base = pick3(a.f, (int)blockIdx.z) + (size_t)iz * a.ny * a.M +
-                         (size_t)tile * a.tb;
+    const size_t tile_off = (size_t)iz * a.ny * a.M + (size_t)tile * a.tb;
+    const float2 *const base = pick3(a.f, (int)blockIdx.z) + tile_off;
     const uint32_t lane = (uint32_t)(t * a.M + b) * 8u;
 
-    if (a.prologue && blk == 0 && blockIdx.z == 0) {
-        const int n = *a.cnt.step;
-        __syncthreads();
-        if (tid == 0) *a.cnt.step = n + 1;
-        for (int e = tid; e < a.src.n_elements; e += blockDim.x) a.src.drive[e] = drive_at(a.src, e, n);
-        for (int h = tid; h < a.n_harm; h += blockDim.x) {
-            const double th = a.harm_wdt * (double)(h + 1) * (double)(n + 1);
-            a.hw[2 * h] = (float)cos(th);
-            a.hw[2 * h + 1] = (float)sin(th);
+    if constexpr (!INV) {
+        // (a call to an out-of-line prologue costs the kernel a stack frame:
+        // scratch memory and more registers for every block)
+        if (a.prologue && blk == 0 && blockIdx.z == 0) {
+            const int n = *a.cnt.step;
+            __syncthreads();
+            if (tid == 0) *a.cnt.step = n + 1;
+            for (int e = tid; e < a.src.n_elements; e += blockDim.x) a.src.drive[e] = drive_at(a.src, e, n);
+            for (int h = tid; h < a.n_harm; h += blockDim.x) {
+                const double th = a.harm_wdt * (double)(h + 1) * (double)(n + 1);
+                a.hw[2 * h] = (float)cos(th);
+                a.hw[2 * h + 1] = (float)sin(th);
+            }
         }
     }
 
@@ -329,10 +334,11 @@ __global__ void __launch_bounds__(MAXT) kw_ypass(YArgs a) {
         __syncthreads();
     }
     if (ok) {
+        float2 *const obase = pick3(a.o, (int)blockIdx.z) + tile_off;
         const size_t jump = (size_t)Eng::out_step(a.plan) * a.M;
 #pragma unroll
         for (int m = 0; m < E; ++m)
-            if (m < cout) st_at(base + m * jump, lane, v[m]);
+            if (m < cout) st_at(obase + m * jump, lane, v[m]);
     }
 }
 
@@ -344,6 +350,7 @@ __global__ void __launch_bounds__(MAXT) kw_ypass(YArgs a) {
 struct ZArgs {
     int zero;                // always 0 (see the salt of the gradient in kw_zfused)
     const float2 *in[3];
+    const float2 *add0[2];   // ABS, ABSM: addends of input 0 (summed as it is loaded), or null
     float2 *out[3];
     GridDev g;
     Tables t;
@@ -351,6 +358,7 @@ struct ZArgs {
     int tb;
     int ntiles;              // column tiles per ky row
     float sa, sb;            // ABSM: c0^2 tau and -c0^2 eta of a homogeneous medium
+                             // (times a factor of input 0's scaling); ABS: sa scales input 0
 };
 
 // kz of FFT index iz (Eq. (5)): m 2 pi / (nz dz), m = iz - nz above the middle
@@ -557,6 +565,18 @@ __global__ void __launch_bounds__(MAXT) kw_zfused(ZArgs a) {
     }
     float2 v[E];
     z_load<Eng>(a, c, (MODE == ZM_ABSM) ? a.in[0] : pick3(a.in, f), v);
+    if constexpr (MODE == ZM_ABS || MODE == ZM_ABSM) {
+        if (f == 0 && a.add0[0]) {                       // block-uniform
+            // input 0 is the sum in[0] + add0[0] + add0[1]
+            float2 w[E];
+            z_load<Eng>(a, c, a.add0[0], w);
+#pragma unroll
+            for (int m = 0; m < E; ++m) v[m] = c_add(v[m], w[m]);
+            z_load<Eng>(a, c, a.add0[1], w);
+#pragma unroll
+            for (int m = 0; m < E; ++m) v[m] = c_add(v[m], w[m]);
+        }
+    }
     stage_table(tws, a.t.tw_z, a.g.nz);
     if constexpr (MODE != ZM_ABS && MODE != ZM_ABSM)
         stage_table(dzl, (MODE == ZM_GRAD || MODE == ZM_GRADT) ? a.t.dpz : a.t.dmz, a.g.nz);
@@ -598,7 +618,8 @@ __global__ void __launch_bounds__(MAXT) kw_zfused(ZArgs a) {
             if (m < cmid) v[m] = c_add(v[m], acc[m]);
         dst = a.out[0];
     } else {
-        z_fwd_op<Eng, MODE>(a, c, o, 1.0f, v);
+        // (ABS: sa scales input 0, the tau term; 1 in the other modes)
+        z_fwd_op<Eng, MODE>(a, c, o, (MODE == ZM_ABS && o == 0) ? a.sa : 1.0f, v);
         dst = pick3(a.out, o);
     }
     Eng::template run<true>(a.pi, tws, t, c.lds, v);
@@ -622,6 +643,7 @@ struct XArgs {
     float *fld[3];           // u or rho components
     float *rho_total;
     int zero;                // always 0; mixed into per-iteration addresses (see salt)
+    int rho0_sum_in_z;       // density pass: the z pass forms FT(rho0 sum du) (constant rho0)
     const float *rsrc;       // xfwd: real input
     float *rdst;             // xinv: real output
     float scale;
@@ -1096,7 +1118,9 @@ __global__ void __launch_bounds__(512) kw_xden(XArgs a) {
         }
     }
     if constexpr (ABS) {
-        row_r2c<Eng>(a, a.Sout[0], b, ok, t, lds, v, tws, tws + M);
+        // (with a constant rho0 the divergence pass forms the spectrum of
+        // rho0 sum du itself: only rho is transformed here)
+        if (!a.rho0_sum_in_z) row_r2c<Eng>(a, a.Sout[0], b, ok, t, lds, v, tws, tws + M);
         row_r2c<Eng>(a, a.Sout[1], b, ok, t, lds, sr, tws, tws + M);
     } else {
         finish_pressure<Eng>(a, line, rr, ok, t, L, b, lds, v, tws, tws + M);
@@ -1246,7 +1270,8 @@ __global__ void __launch_bounds__(512) kw_xden3(XArgs a) {
     __syncthreads();
     if constexpr (ABS) {
         float2 *dst = (g == 0) ? a.Sout[0] : a.Sout[1];
-        row_r2c<Eng, false>(a, dst, b, ok && g < 2, t, lds, v, tws, twp);
+        const bool out = g == 1 || (g == 0 && !a.rho0_sum_in_z);
+        row_r2c<Eng, false>(a, dst, b, ok && out, t, lds, v, tws, twp);
     } else {
         finish_pressure<Eng>(a, line, rr, ok && g == 1, t, L, b, lds, v, tws, twp);
     }

@@ -54,8 +54,9 @@ hipError_t launch_xvel(hipStream_t s, const GridDev &g, const LaunchCfg &c, cons
 hipError_t launch_xden(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
                        const Medium &m, const SourceDev &src, const SensorDev &sen,
                        const Counters &cnt, float2 *const *Sin, float *const *rho,
-                       float *rho_total, float2 *const *Sout) {
+                       float *rho_total, float2 *const *Sout, bool rho0_sum_in_z) {
     XArgs a = make_xargs(g, c, t);
+    a.rho0_sum_in_z = rho0_sum_in_z ? 1 : 0;
     a.m = m;
     a.src = src;
     a.sen = sen;

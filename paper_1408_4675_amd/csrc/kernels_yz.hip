@@ -5,9 +5,13 @@ namespace kw {
 
 hipError_t launch_ypass(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
                         float2 *const *fields, int nfields, bool inverse,
-                        const Counters *prologue, const SourceDev *src, const SensorDev *sen) {
+                        const Counters *prologue, const SourceDev *src, const SensorDev *sen,
+                        float2 *const *dst) {
     YArgs a{};
-    for (int i = 0; i < nfields; ++i) a.f[i] = fields[i];
+    for (int i = 0; i < nfields; ++i) {
+        a.f[i] = fields[i];
+        a.o[i] = dst ? dst[i] : fields[i];
+    }
     a.M = g.M;
     a.ny = g.ny;
     a.plan = inverse ? c.pyi : c.py;
@@ -69,10 +73,15 @@ static ZArgs make_zargs(const GridDev &g, const LaunchCfg &c, const Tables &t, i
 }
 
 hipError_t launch_zfused(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
-                         int mode, float2 *const *in, float2 *const *out, float sa, float sb) {
+                         int mode, float2 *const *in, float2 *const *out, float sa, float sb,
+                         float2 *const *add0) {
     ZArgs a = make_zargs(g, c, t, mode, in, out);
     a.sa = sa;
     a.sb = sb;
+    if (add0 && (mode == ZM_ABS || mode == ZM_ABSM)) {
+        a.add0[0] = add0[0];
+        a.add0[1] = add0[1];
+    }
     const bool fixed_z = eng_fixed(c.eng_z);
     if (mode == ZM_ABSM && a.tb * c.pz.L > 512 && a.tb > 1) {
         // the merged absorption holds two spectra per thread: they do not fit

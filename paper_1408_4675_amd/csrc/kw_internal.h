@@ -189,6 +189,9 @@ inline size_t zcol_lds_bytes(int n, int tb) {
 // ABSM: ta k^(y-2) / N on input 0 plus tb k^(y-1) / N on input 1, summed into
 // one output (the two absorption terms of Eq. (8) for a medium whose
 // c0^2 tau and c0^2 eta are scalars: one inverse transform instead of two)
+// ABS and ABSM take an optional pair of addends of input 0 (add0): with a
+// constant rho0 input 0 is then the sum of the three divergence outputs, and
+// sa carries rho0 nx ny (see enqueue_step)
 enum { ZM_GRAD = 0, ZM_DIV = 1, ZM_ABS = 2, ZM_DIVT = 3, ZM_GRADT = 4, ZM_ABSM = 5 };
 
 // reverse-mode (adjoint) step state, all device arrays of N floats unless noted
@@ -219,17 +222,17 @@ struct AdjDev {
 hipError_t launch_ypass(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
                         float2 *const *fields, int nfields, bool inverse,
                         const Counters *prologue, const SourceDev *src,
-                        const SensorDev *sen = nullptr);
+                        const SensorDev *sen = nullptr, float2 *const *dst = nullptr);
 hipError_t launch_zfused(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
                          int mode, float2 *const *in, float2 *const *out, float sa = 1.0f,
-                         float sb = 1.0f);
+                         float sb = 1.0f, float2 *const *add0 = nullptr);
 hipError_t launch_xvel(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
                        const Medium &m, float2 *const *S, float *const *u,
                        const SourceDev &src, const SensorDev &sen, const Counters &cnt);
 hipError_t launch_xden(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
                        const Medium &m, const SourceDev &src, const SensorDev &sen,
                        const Counters &cnt, float2 *const *Sin, float *const *rho,
-                       float *rho_total, float2 *const *Sout);
+                       float *rho_total, float2 *const *Sout, bool rho0_sum_in_z = false);
 hipError_t launch_xeos(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
                        const Medium &m, const SourceDev &src, const SensorDev &sen,
                        const Counters &cnt, float2 *const *Sin, const float *rho_total,

@@ -73,15 +73,17 @@ hipError_t launch_fill_int(hipStream_t, int *p, size_t n, int v) {
 }
 hipError_t launch_ypass(hipStream_t, const GridDev &, const LaunchCfg &, const Tables &,
                         float2 *const *, int, bool, const Counters *, const SourceDev *,
-                        const SensorDev *) { return launch_status(); }
+                        const SensorDev *, float2 *const *) { return launch_status(); }
 hipError_t launch_zfused(hipStream_t, const GridDev &, const LaunchCfg &, const Tables &, int,
-                         float2 *const *, float2 *const *, float, float) { return launch_status(); }
+                         float2 *const *, float2 *const *, float, float, float2 *const *) {
+    return launch_status();
+}
 hipError_t launch_xvel(hipStream_t, const GridDev &, const LaunchCfg &, const Tables &,
                        const Medium &, float2 *const *, float *const *, const SourceDev &,
                        const SensorDev &, const Counters &) { return launch_status(); }
 hipError_t launch_xden(hipStream_t, const GridDev &, const LaunchCfg &, const Tables &,
                        const Medium &, const SourceDev &, const SensorDev &, const Counters &,
-                       float2 *const *, float *const *, float *, float2 *const *) {
+                       float2 *const *, float *const *, float *, float2 *const *, bool) {
     return launch_status();
 }
 hipError_t launch_xeos(hipStream_t, const GridDev &, const LaunchCfg &, const Tables &,

@@ -338,6 +338,33 @@ def test_parity_merged_absorption(kw, shape):
     sim, orc = _run_both(kw, scen, 8)
     st = sim.stats()
     assert st["fft_inverse_per_step"] == 7            # the merged path ran
+    assert st["fft_forward_per_step"] == 5            # constant rho0: no transform of rho0 sum du
+    errs, tol = compare_outputs(sim, orc, scen, REPORT)
+    for k, e in errs.items():
+        assert e <= tol, (k, e)
+
+
+# Absorbing media with a constant rho0 and maps of c0 and alpha0: the
+# divergence z pass forms the tau term's spectrum from the sum of the three
+# divergence spectra (DIVA) and the absorption pass transforms rho alone
+# (ABSR, terms kept apart since c0^2 tau and c0^2 eta are maps).  Fixed and
+# generic z engines, even ny (double rows 0 and ny/2) and odd ny, 1024-point
+# columns.
+RHO0C = [(48, 20, 18), (64, 36, 30), (40, 45, 27), (32, 8, 1024), (32, 32, 32)]
+
+
+@pytest.mark.parametrize("shape", RHO0C, ids=["%dx%dx%d" % s for s in RHO0C])
+def test_parity_constant_rho0_absorbing(kw, shape):
+    nx, ny, nz = shape
+    scen = sc.small_case(nx, ny, nz, seed=17, heterogeneous=True, nonlinear=True,
+                         absorbing=True, pml=2, steps=10, sensor_mask=True, amp=2e6)
+    med = scen.medium
+    scen = scen.replace(name="rho0c_" + scen.name,
+                        medium=sc.Medium(med.c0, 1000.0, med.alpha0, med.bona, alpha_power=1.5,
+                                         nonlinear=True, absorbing=True))
+    sim, orc = _run_both(kw, scen, 10)
+    st = sim.stats()
+    assert (st["fft_forward_per_step"], st["fft_inverse_per_step"]) == (5, 8)
     errs, tol = compare_outputs(sim, orc, scen, REPORT)
     for k, e in errs.items():
         assert e <= tol, (k, e)
