@@ -311,6 +311,20 @@ int kw_load(kw_sim *sim, const void *src, size_t src_bytes, int src_is_device);
  *                      KW_ESTATE; call it for n = n_steps-1 down to 0.  Between
  *                      reverse steps the simulation may be stepped or loaded
  *                      freely (the adjoint state lives in its own workspace).
+ *   kw_adjoint_record  advances `sim` by one step, as kw_step(sim, 1) does
+ *                      (launched without the step graph), and writes to
+ *                      dev_record (device memory, kw_adjoint_record_bytes)
+ *                      what the reverse step needs of it: du_x, du_y, du_z of
+ *                      Eq. (4c), rho_x, rho_y, rho_z after Eq. (4d) and the
+ *                      packed spectrum of the new pressure.  KW_EINVAL for a
+ *                      short buffer.  Asynchronous on the simulation's stream.
+ *   kw_adjoint_step_record  reverse step n reading the forward state from a
+ *                      record of forward step n made by kw_adjoint_record
+ *                      (the caller keeps each record with its step); `sim`
+ *                      may hold any state.  Without recomputing du_xi and
+ *                      without restoring a snapshot, it is the cheaper way to
+ *                      run a checkpointed sweep: restore a checkpoint, record
+ *                      the steps up to the next one, reverse them.
  *   kw_adjoint_objective  J of the forward run, once `sim` holds the state after
  *                      its last step n_steps - 1 (needs p_rms or intensity
  *                      recorded at every point); float64 sum on the device
@@ -324,6 +338,9 @@ int kw_adjoint_create(kw_sim *sim, const float *weights, int32_t n_steps, void *
                       size_t ws_bytes, kw_adj **out);
 int kw_adjoint_objective(kw_adj *adj, double *J);
 int kw_adjoint_step(kw_adj *adj, int32_t n);
+int64_t kw_adjoint_record_bytes(kw_adj *adj);
+int kw_adjoint_record(kw_adj *adj, void *dev_record, size_t bytes);
+int kw_adjoint_step_record(kw_adj *adj, int32_t n, const void *dev_record, size_t bytes);
 int kw_adjoint_source_gradient(kw_adj *adj, double *dJds, size_t dst_bytes);
 int kw_adjoint_gradient(kw_adj *adj, double *grad_amp, double *grad_phase);
 int kw_adjoint_destroy(kw_adj *adj);

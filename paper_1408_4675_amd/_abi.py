@@ -50,6 +50,7 @@ EXPORTS = ("kw_workspace_size", "kw_create", "kw_prepare", "kw_plan_workspace_si
            "kw_set_field", "kw_gather_field", "kw_profile", "kw_stats", "kw_set_graph",
            "kw_set_plan", "kw_state_bytes", "kw_save", "kw_load", "kw_adjoint_workspace_size",
            "kw_adjoint_create", "kw_adjoint_objective", "kw_adjoint_step", "kw_adjoint_source_gradient",
+           "kw_adjoint_record_bytes", "kw_adjoint_record", "kw_adjoint_step_record",
            "kw_adjoint_gradient", "kw_adjoint_destroy", "kw_destroy", "kw_last_error")
 
 
@@ -170,6 +171,12 @@ def _load(path):
     lib.kw_adjoint_objective.argtypes = [C.c_void_p, P(C.c_double)]
     lib.kw_adjoint_step.restype = C.c_int
     lib.kw_adjoint_step.argtypes = [C.c_void_p, C.c_int32]
+    lib.kw_adjoint_record_bytes.restype = C.c_int64
+    lib.kw_adjoint_record_bytes.argtypes = [C.c_void_p]
+    lib.kw_adjoint_record.restype = C.c_int
+    lib.kw_adjoint_record.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
+    lib.kw_adjoint_step_record.restype = C.c_int
+    lib.kw_adjoint_step_record.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t]
     lib.kw_adjoint_source_gradient.restype = C.c_int
     lib.kw_adjoint_source_gradient.argtypes = [C.c_void_p, P(C.c_double), C.c_size_t]
     lib.kw_adjoint_gradient.restype = C.c_int

@@ -4,9 +4,11 @@ J = sum_x w(x) I(x), I the time-mean intensity over the recorded steps, is
 differentiated through the float32 time stepping by the library's reverse-mode
 step (kw_adjoint_*).  The forward run keeps a snapshot (kw_save) every
 `checkpoint_every` steps; the reverse sweep walks the segments backwards,
-re-runs each segment forward from its snapshot keeping the state after every
-step, and applies the reverse steps from the last to the first.  Device memory:
-one snapshot per segment plus one per step of a segment.
+restores each segment's snapshot, re-runs the segment forward writing a step
+record (kw_adjoint_record: the divergence, the density components and the
+pressure spectrum of the step) for every step, and applies the reverse steps
+from the last to the first, each reading its record.  Device memory: one
+snapshot per segment plus one record (7 fields) per step of a segment.
 
 `FocusObjective` wraps this as a torch.autograd.Function of the element
 amplitudes and phases.  This module only sequences library calls.
@@ -57,6 +59,25 @@ class Adjoint:
     def step(self, n: int):
         A.check(self.lib.kw_adjoint_step(self.handle, int(n)))
 
+    def record_bytes(self) -> int:
+        return int(self.lib.kw_adjoint_record_bytes(self.handle))
+
+    def new_record(self) -> torch.Tensor:
+        """A device buffer for one step record, ordered before the simulation's stream."""
+        r = torch.empty(self.record_bytes(), dtype=torch.uint8, device=self.sim.device)
+        self.sim.stream.wait_stream(torch.cuda.current_stream(self.sim.device))
+        return r
+
+    def record(self, rec: torch.Tensor):
+        """Advance the simulation one step, writing that step's record to rec."""
+        A.check(self.lib.kw_adjoint_record(self.handle, C.c_void_p(rec.data_ptr()),
+                                           C.c_size_t(rec.numel())))
+
+    def step_record(self, n: int, rec: torch.Tensor):
+        """Reverse step n from the record of forward step n."""
+        A.check(self.lib.kw_adjoint_step_record(self.handle, int(n), C.c_void_p(rec.data_ptr()),
+                                                C.c_size_t(rec.numel())))
+
     def source_gradient(self) -> np.ndarray:
         ne = len(self.sim.scenario.source.amp)
         out = np.zeros((self.n_steps, ne), np.float64)
@@ -96,6 +117,7 @@ class _Run:
         self.T = int(scen.steps)
         self.sim = Simulation(scen, device=device)
         self.adj = Adjoint(self.sim, weights, self.T)
+        self.records = [self.adj.new_record() for _ in range(min(self.K, self.T))]
         self.ckpt = {}
         t0 = time.perf_counter()
         for n0 in range(0, self.T, self.K):
@@ -110,14 +132,10 @@ class _Run:
         for n0 in sorted(self.ckpt, reverse=True):
             n1 = min(n0 + self.K, self.T)
             sim.load(self.ckpt[n0])
-            tape = []
-            for _ in range(n0, n1):
-                sim.step(1)
-                tape.append(sim.save(device=True))
+            for j in range(n1 - n0):
+                adj.record(self.records[j])
             for n in range(n1 - 1, n0 - 1, -1):
-                sim.load(tape[n - n0])
-                adj.step(n)
-            del tape
+                adj.step_record(n, self.records[n - n0])
         ga, gp = adj.gradient()
         sim.synchronize()
         self.backward_s = time.perf_counter() - t0
@@ -125,6 +143,7 @@ class _Run:
 
     def close(self):
         self.adj.close()
+        self.records = None
         self.sim.close()
 
 

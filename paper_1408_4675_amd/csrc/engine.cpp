@@ -475,6 +475,8 @@ struct kw_sim {
     bool merged_abs = false;           // absorption terms merged (scalar c0^2 tau, c0^2 eta)
     bool rho0_sum_in_z = false;        // absorbing with a constant rho0: the divergence
                                        // pass forms the spectrum of rho0 sum du
+    float *rec[6] = {};                // while a step is recorded for the reverse mode:
+                                       // where du_xi and the new rho_xi go (else null)
     // host copy of the source set-up (for the reverse-mode step)
     std::vector<int> src_flat, src_elem;
     std::vector<float> src_coef;
@@ -573,6 +575,7 @@ hipError_t enqueue_step(kw_sim *s) {
     float2 *s0[1] = {S[0]};
     float2 *s123[3] = {S[1], S[2], S[3]};
     float2 *s456[3] = {S[4], S[5], S[6]};
+    float *const *rec = s->rec[0] ? s->rec : nullptr;
     KW_L(KC_YFWD, 2, launch_ypass(st, g, c, t, s0, 1, false, &s->counters, &s->src, &s->sen));
     KW_L(KC_ZGRAD, 4, launch_zfused(st, g, c, t, ZM_GRAD, s0, s123));
     KW_L(KC_YINV, 6, launch_ypass(st, g, c, t, s123, 3, true, nullptr, nullptr));
@@ -592,7 +595,7 @@ hipError_t enqueue_step(kw_sim *s) {
         KW_L(KC_YINV, 6, launch_ypass(st, g, c, t, s456, 3, true, nullptr, nullptr, nullptr, s123));
         float2 *rho_out[2] = {S[0], S[0]};
         KW_L(KC_XDEN, 11, launch_xden(st, g, c, t, s->med, s->src, s->sen, s->counters, s123,
-                                      s->buf.rho, s->buf.rho_total, rho_out, true));
+                                      s->buf.rho, s->buf.rho_total, rho_out, true, rec));
         KW_L(KC_YFWD, 2, launch_ypass(st, g, c, t, s0, 1, false, nullptr, nullptr));
         float2 *in[2] = {S[4], S[0]};
         float2 *add0[2] = {S[5], S[6]};
@@ -623,7 +626,7 @@ hipError_t enqueue_step(kw_sim *s) {
         float2 *out2[2] = {S[1], S[2]};
         KW_L(KC_XDEN, 12 + (ms.het[MED_RHO0] ? 1 : 0),
              launch_xden(st, g, c, t, s->med, s->src, s->sen, s->counters, s456, s->buf.rho,
-                         s->buf.rho_total, out2));
+                         s->buf.rho_total, out2, false, rec));
         float2 *s12[2] = {S[1], S[2]};
         float2 *s45[2] = {S[4], S[5]};
         KW_L(KC_YFWD, 4, launch_ypass(st, g, c, t, s12, 2, false, nullptr, nullptr));
@@ -650,7 +653,7 @@ hipError_t enqueue_step(kw_sim *s) {
                                  (ms.het[MED_NL] ? 1 : 0);
         KW_L(KC_XDEN, 10 + med_units + sens_units,
              launch_xden(st, g, c, t, s->med, s->src, s->sen, s->counters, s456, s->buf.rho,
-                         nullptr, out1));
+                         nullptr, out1, false, rec));
     }
 #undef KW_L
     s->kernels_per_step = nk;
@@ -1779,13 +1782,21 @@ int kw_adjoint_create(kw_sim *s, const float *weights, int32_t n_steps, void *de
     return KW_OK;
 }
 
-int kw_adjoint_step(kw_adj *adj, int32_t n) {
-    if (!adj) return fail(KW_EINVAL, "adj is NULL");
+namespace {
+
+// layout of a step record: du_x, du_y, du_z, rho_x, rho_y, rho_z, the packed
+// spectrum of p (one N-float slot each, 256-byte aligned)
+size_t record_slot(const kw_sim *s) {
+    const size_t N = (size_t)s->grid.nx * s->grid.ny * s->grid.nz;
+    return (N * sizeof(float) + 255) / 256 * 256;
+}
+
+// Reverse step n.  rec: a record of forward step n, or null when the
+// simulation holds the state after step n (the forward divergence is then
+// recomputed from u^(n+1/2)).
+int reverse_step(kw_adj *adj, int n, const char *rec) {
     kw_sim *s = adj->sim;
-    if (n < 0 || n >= adj->n_steps) return fail(KW_EINVAL, "step %d outside [0, %d)", n, adj->n_steps);
-    if (s->steps != (long)n + 1)
-        return fail(KW_ESTATE, "the simulation holds the state after step %ld, not %d", s->steps - 1, n);
-    AdjDev &a = adj->a;
+    AdjDev a = adj->a;
     hipStream_t st = s->stream;
     const GridDev &g = s->g;
     const Medium &m = s->med;
@@ -1795,14 +1806,29 @@ int kw_adjoint_step(kw_adj *adj, int32_t n) {
         if ((e = (call)) != hipSuccess)                                             \
             return fail(KW_EDEVICE, "adjoint step: %s", hipGetErrorString(e));      \
     } while (0)
-    // forward divergence of u^(n+1/2) (the nonlinear denominators need it)
-    KW_A(spectral(s, ZM_DIV, s->buf.u, a.d, 3));
+    const float2 *p_spec;
+    if (rec) {
+        const size_t slot = record_slot(s);
+        for (int i = 0; i < 3; ++i) {
+            a.dfw[i] = reinterpret_cast<const float *>(rec + i * slot);
+            a.rho[i] = reinterpret_cast<const float *>(rec + (3 + i) * slot);
+        }
+        p_spec = reinterpret_cast<const float2 *>(rec + 6 * slot);
+    } else {
+        // forward divergence of u^(n+1/2) (the nonlinear denominators need it)
+        KW_A(spectral(s, ZM_DIV, s->buf.u, a.d, 3));
+        for (int i = 0; i < 3; ++i) {
+            a.dfw[i] = a.d[i];
+            a.rho[i] = s->buf.rho[i];
+        }
+        p_spec = s->buf.S[0];
+    }
     const bool loss = n + 1 >= s->record_start;
-    if (loss) KW_A(launch_xinv(st, g, s->cfg, s->tab, s->buf.S[0], a.pf, 1.0f / (float)s->grid.nx));
-    KW_A(launch_adj_eos(st, g, m, a, s->buf.rho, loss));
+    if (loss) KW_A(launch_xinv(st, g, s->cfg, s->tab, p_spec, a.pf, 1.0f / (float)s->grid.nx));
+    KW_A(launch_adj_eos(st, g, m, a, loss));
     if (m.absorbing) KW_A(spectral(s, ZM_ABS, a.T, a.T, 2));
     KW_A(launch_adj_src(st, g, m, a, s->src, n));
-    KW_A(launch_adj_den(st, g, s->tab, m, a, s->buf.rho));
+    KW_A(launch_adj_den(st, g, s->tab, m, a));
     KW_A(launch_adj_src_fix(st, a, m));
     KW_A(spectral(s, ZM_DIVT, a.d, a.T, 3));
     KW_A(launch_adj_vel(st, g, s->tab, m, a));
@@ -1810,6 +1836,48 @@ int kw_adjoint_step(kw_adj *adj, int32_t n) {
     KW_A(launch_adj_sum(st, g, a));
 #undef KW_A
     return KW_OK;
+}
+
+}  // namespace
+
+int kw_adjoint_step(kw_adj *adj, int32_t n) {
+    if (!adj) return fail(KW_EINVAL, "adj is NULL");
+    kw_sim *s = adj->sim;
+    if (n < 0 || n >= adj->n_steps) return fail(KW_EINVAL, "step %d outside [0, %d)", n, adj->n_steps);
+    if (s->steps != (long)n + 1)
+        return fail(KW_ESTATE, "the simulation holds the state after step %ld, not %d", s->steps - 1, n);
+    return reverse_step(adj, n, nullptr);
+}
+
+int64_t kw_adjoint_record_bytes(kw_adj *adj) {
+    if (!adj) return -1;
+    return (int64_t)(7 * record_slot(adj->sim));
+}
+
+int kw_adjoint_record(kw_adj *adj, void *dev_record, size_t bytes) {
+    if (!adj || !dev_record) return fail(KW_EINVAL, "NULL argument");
+    kw_sim *s = adj->sim;
+    const size_t slot = record_slot(s);
+    if (bytes < 7 * slot) return fail(KW_EINVAL, "record has %zu bytes, %zu needed", bytes, 7 * slot);
+    char *r = reinterpret_cast<char *>(dev_record);
+    for (int i = 0; i < 6; ++i) s->rec[i] = reinterpret_cast<float *>(r + i * slot);
+    const hipError_t e = enqueue_step(s);
+    for (int i = 0; i < 6; ++i) s->rec[i] = nullptr;
+    if (e != hipSuccess) return fail(KW_EDEVICE, "kernel launch: %s", hipGetErrorString(e));
+    const size_t N = (size_t)s->grid.nx * s->grid.ny * s->grid.nz;
+    KW_HIP(hipMemcpyAsync(r + 6 * slot, s->buf.S[0], N * sizeof(float), hipMemcpyDeviceToDevice,
+                          s->stream));
+    s->steps += 1;
+    s->stepped = true;
+    return KW_OK;
+}
+
+int kw_adjoint_step_record(kw_adj *adj, int32_t n, const void *dev_record, size_t bytes) {
+    if (!adj || !dev_record) return fail(KW_EINVAL, "NULL argument");
+    if (n < 0 || n >= adj->n_steps) return fail(KW_EINVAL, "step %d outside [0, %d)", n, adj->n_steps);
+    const size_t need = 7 * record_slot(adj->sim);
+    if (bytes < need) return fail(KW_EINVAL, "record has %zu bytes, %zu needed", bytes, need);
+    return reverse_step(adj, n, reinterpret_cast<const char *>(dev_record));
 }
 
 int kw_adjoint_objective(kw_adj *adj, double *J) {

@@ -48,16 +48,14 @@ __global__ void __launch_bounds__(kThreads) kw_adj_weights(GridDev g, Medium m, 
     }
 }
 
-__global__ void __launch_bounds__(kThreads) kw_adj_eos(GridDev g, Medium m, AdjDev a,
-                                                        const float *r0, const float *r1,
-                                                        const float *r2, int loss) {
+__global__ void __launch_bounds__(kThreads) kw_adj_eos(GridDev g, Medium m, AdjDev a, int loss) {
     const size_t N = npoints(g);
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
          i += (size_t)gridDim.x * blockDim.x) {
         float pbar = a.pb[i];
         if (loss) pbar += a.w[i] * a.pf[i];
         float c = coef_at(m.c0sq, i);
-        if (m.nonlinear) c += 2.0f * coef_at(m.nl, i) * (r0[i] + r1[i] + r2[i]);
+        if (m.nonlinear) c += 2.0f * coef_at(m.nl, i) * (a.rho[0][i] + a.rho[1][i] + a.rho[2][i]);
         a.rbt[i] = c * pbar;
         if (m.absorbing) {
             a.T[0][i] = coef_at(m.ta, i) * pbar;
@@ -82,7 +80,7 @@ __global__ void __launch_bounds__(kThreads) kw_adj_src(GridDev g, Medium m, AdjD
         rsum += R;
         float c = 0.0f;
         if (m.nonlinear) {
-            const float den = 1.0f + 2.0f * g.dt * pick3v(a.d[0], a.d[1], a.d[2], x)[f];
+            const float den = 1.0f + 2.0f * g.dt * pick3v(a.dfw[0], a.dfw[1], a.dfw[2], x)[f];
             c = R * 2.0f * g.dt * add / den;
         }
         a.corr[(size_t)x * a.n_src + k] = c;
@@ -116,9 +114,7 @@ __global__ void __launch_bounds__(kThreads) kw_adj_src_sum(AdjDev a, int n) {
     if (threadIdx.x == 0) a.dJds[(size_t)n * a.n_elem + e] = total;
 }
 
-__global__ void __launch_bounds__(kThreads) kw_adj_den(GridDev g, Tables t, Medium m, AdjDev a,
-                                                        const float *r0, const float *r1,
-                                                        const float *r2) {
+__global__ void __launch_bounds__(kThreads) kw_adj_den(GridDev g, Tables t, Medium m, AdjDev a) {
     const size_t N = npoints(g);
     const float dt = g.dt;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
@@ -137,8 +133,8 @@ __global__ void __launch_bounds__(kThreads) kw_adj_den(GridDev g, Tables t, Medi
             const float R = rb[i] + rbt;
             float den = 1.0f, dbar;
             if (m.nonlinear) {
-                den = 1.0f + 2.0f * dt * d[i];
-                const float rn = pick3v(r0, r1, r2, x)[i];
+                den = 1.0f + 2.0f * dt * pick3v(a.dfw[0], a.dfw[1], a.dfw[2], x)[i];
+                const float rn = pick3v(a.rho[0], a.rho[1], a.rho[2], x)[i];
                 dbar = -R * (q * dt * rho0 + 2.0f * dt * rn) / den;
             } else {
                 dbar = -R * q * dt * rho0;
@@ -231,10 +227,9 @@ hipError_t launch_adj_weights(hipStream_t s, const GridDev &g, const Medium &m, 
 }
 
 hipError_t launch_adj_eos(hipStream_t s, const GridDev &g, const Medium &m, const AdjDev &a,
-                          float *const *rho, bool loss) {
+                          bool loss) {
     const size_t N = (size_t)g.nx * g.rows;
-    hipLaunchKernelGGL(kw_adj_eos, grid_for(N), dim3(kThreads), 0, s, g, m, a, rho[0], rho[1],
-                       rho[2], loss ? 1 : 0);
+    hipLaunchKernelGGL(kw_adj_eos, grid_for(N), dim3(kThreads), 0, s, g, m, a, loss ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -250,10 +245,9 @@ hipError_t launch_adj_src(hipStream_t s, const GridDev &g, const Medium &m, cons
 }
 
 hipError_t launch_adj_den(hipStream_t s, const GridDev &g, const Tables &t, const Medium &m,
-                          const AdjDev &a, float *const *rho) {
+                          const AdjDev &a) {
     const size_t N = (size_t)g.nx * g.rows;
-    hipLaunchKernelGGL(kw_adj_den, grid_for(N), dim3(kThreads), 0, s, g, t, m, a, rho[0], rho[1],
-                       rho[2]);
+    hipLaunchKernelGGL(kw_adj_den, grid_for(N), dim3(kThreads), 0, s, g, t, m, a);
     return hipGetLastError();
 }
 

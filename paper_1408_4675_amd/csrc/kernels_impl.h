@@ -644,6 +644,8 @@ struct XArgs {
     float *rho_total;
     int zero;                // always 0; mixed into per-iteration addresses (see salt)
     int rho0_sum_in_z;       // density pass: the z pass forms FT(rho0 sum du) (constant rho0)
+    float *rec_d[3];         // density pass, when recording a step for the reverse mode: the
+    float *rec_rho[3];       // divergence components du_xi and the new rho_xi (else null)
     const float *rsrc;       // xfwd: real input
     float *rdst;             // xinv: real output
     float scale;
@@ -1087,6 +1089,10 @@ __global__ void __launch_bounds__(512) kw_xden(XArgs a) {
                         if (has_src) nw = c_add(nw, sv[m]);
                     }
                     st2(rho, i, nw);
+                    if (a.rec_d[0]) {                    // block-uniform
+                        st2(pick3(a.rec_d, g), i, d);
+                        st2(pick3(a.rec_rho, g), i, nw);
+                    }
                     sr[m] = c_add(sr[m], nw);
                     if constexpr (ABS) sd[m] = c_add(sd[m], d);
                 }
@@ -1221,6 +1227,10 @@ __global__ void __launch_bounds__(512) kw_xden3(XArgs a) {
                         nw.y += mysrc[x + 1];
                     }
                     st2(rho, i, nw);
+                    if (a.rec_d[0]) {                    // block-uniform
+                        st2(pick3(a.rec_d, g), i, d);
+                        st2(pick3(a.rec_rho, g), i, nw);
+                    }
                 }
                 if (g == 1) {
                     buf1[n] = d;

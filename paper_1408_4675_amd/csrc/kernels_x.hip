@@ -54,9 +54,16 @@ hipError_t launch_xvel(hipStream_t s, const GridDev &g, const LaunchCfg &c, cons
 hipError_t launch_xden(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
                        const Medium &m, const SourceDev &src, const SensorDev &sen,
                        const Counters &cnt, float2 *const *Sin, float *const *rho,
-                       float *rho_total, float2 *const *Sout, bool rho0_sum_in_z) {
+                       float *rho_total, float2 *const *Sout, bool rho0_sum_in_z,
+                       float *const *rec) {
     XArgs a = make_xargs(g, c, t);
     a.rho0_sum_in_z = rho0_sum_in_z ? 1 : 0;
+    if (rec) {
+        for (int i = 0; i < 3; ++i) {
+            a.rec_d[i] = rec[i];
+            a.rec_rho[i] = rec[3 + i];
+        }
+    }
     a.m = m;
     a.src = src;
     a.sen = sen;

@@ -199,7 +199,10 @@ struct AdjDev {
     float *pb;               // adjoint of p^(n+1) (carried between reverse steps)
     float *ub[3];            // adjoint of u^(n+1/2)
     float *rb[3];            // adjoint of rho_xi^(n+1)
-    float *d[3];             // forward divergence d_xi, then its adjoint
+    float *d[3];             // adjoint of the divergence d_xi (the forward d_xi first, when
+                             // it is recomputed rather than read from a step record)
+    const float *dfw[3];     // forward divergence d_xi of the step being reversed
+    const float *rho[3];     // forward rho_xi after that step
     float *T[3];             // temporaries
     float *pf;               // p^(n+1)
     float *w;                // 2 w / (rho0 c0 N_w): derivative of the objective
@@ -232,7 +235,8 @@ hipError_t launch_xvel(hipStream_t s, const GridDev &g, const LaunchCfg &c, cons
 hipError_t launch_xden(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
                        const Medium &m, const SourceDev &src, const SensorDev &sen,
                        const Counters &cnt, float2 *const *Sin, float *const *rho,
-                       float *rho_total, float2 *const *Sout, bool rho0_sum_in_z = false);
+                       float *rho_total, float2 *const *Sout, bool rho0_sum_in_z = false,
+                       float *const *rec = nullptr);
 hipError_t launch_xeos(hipStream_t s, const GridDev &g, const LaunchCfg &c, const Tables &t,
                        const Medium &m, const SourceDev &src, const SensorDev &sen,
                        const Counters &cnt, float2 *const *Sin, const float *rho_total,
@@ -246,11 +250,11 @@ hipError_t launch_xinv(hipStream_t s, const GridDev &g, const LaunchCfg &c, cons
 hipError_t launch_adj_weights(hipStream_t s, const GridDev &g, const Medium &m, float *w,
                               float scale);
 hipError_t launch_adj_eos(hipStream_t s, const GridDev &g, const Medium &m, const AdjDev &a,
-                          float *const *rho, bool loss);
+                          bool loss);
 hipError_t launch_adj_src(hipStream_t s, const GridDev &g, const Medium &m, const AdjDev &a,
                           const SourceDev &src, int n);
 hipError_t launch_adj_den(hipStream_t s, const GridDev &g, const Tables &t, const Medium &m,
-                          const AdjDev &a, float *const *rho);
+                          const AdjDev &a);
 hipError_t launch_adj_src_fix(hipStream_t s, const AdjDev &a, const Medium &m);
 hipError_t launch_adj_vel(hipStream_t s, const GridDev &g, const Tables &t, const Medium &m,
                           const AdjDev &a);

@@ -83,7 +83,8 @@ hipError_t launch_xvel(hipStream_t, const GridDev &, const LaunchCfg &, const Ta
                        const SensorDev &, const Counters &) { return launch_status(); }
 hipError_t launch_xden(hipStream_t, const GridDev &, const LaunchCfg &, const Tables &,
                        const Medium &, const SourceDev &, const SensorDev &, const Counters &,
-                       float2 *const *, float *const *, float *, float2 *const *, bool) {
+                       float2 *const *, float *const *, float *, float2 *const *, bool,
+                       float *const *) {
     return launch_status();
 }
 hipError_t launch_xeos(hipStream_t, const GridDev &, const LaunchCfg &, const Tables &,
@@ -97,11 +98,11 @@ hipError_t launch_adj_weights(hipStream_t, const GridDev &, const Medium &, floa
     return launch_status();
 }
 hipError_t launch_adj_eos(hipStream_t, const GridDev &, const Medium &, const AdjDev &,
-                          float *const *, bool) { return launch_status(); }
+                          bool) { return launch_status(); }
 hipError_t launch_adj_src(hipStream_t, const GridDev &, const Medium &, const AdjDev &,
                           const SourceDev &, int) { return launch_status(); }
 hipError_t launch_adj_den(hipStream_t, const GridDev &, const Tables &, const Medium &,
-                          const AdjDev &, float *const *) { return launch_status(); }
+                          const AdjDev &) { return launch_status(); }
 hipError_t launch_adj_src_fix(hipStream_t, const AdjDev &, const Medium &) { return launch_status(); }
 hipError_t launch_adj_vel(hipStream_t, const GridDev &, const Tables &, const Medium &,
                           const AdjDev &) { return launch_status(); }
