@@ -1648,23 +1648,23 @@ struct kw_adj {
 namespace {
 
 struct AdjLayout {
-    size_t fld[16];          // pb, ub x3, rb x3, d x3, T x3, pf, w, rbt
-    size_t dJds, obj, flat, elem, coef, corr, share, eptr, epts, partials, total;
+    size_t fld[12];          // pb, ub x3, rb x3, d x3, w, rbt
+    size_t dJds, obj, flat, elem, coef, add, rsrc, eptr, epts, partials, total;
 };
 
 AdjLayout adj_layout(const kw_sim *s, int n_steps) {
     AdjLayout L{};
     Carver cv;
     const size_t N = (size_t)s->grid.nx * s->grid.ny * s->grid.nz;
-    for (int i = 0; i < 16; ++i) L.fld[i] = cv.take(N * sizeof(float));
+    for (int i = 0; i < 12; ++i) L.fld[i] = cv.take(N * sizeof(float));
     const size_t ns = s->src_flat.size();
     L.dJds = cv.take((size_t)std::max(1, n_steps) * std::max(1, s->cnt.n_elem) * sizeof(double));
     L.obj = cv.take(sizeof(double));
     L.flat = cv.take(std::max<size_t>(ns, 1) * sizeof(int));
     L.elem = cv.take(std::max<size_t>(ns, 1) * sizeof(int));
     L.coef = cv.take(std::max<size_t>(ns, 1) * sizeof(float));
-    L.corr = cv.take(3 * std::max<size_t>(ns, 1) * sizeof(float));
-    L.share = cv.take(std::max<size_t>(ns, 1) * sizeof(double));
+    L.add = cv.take(std::max<size_t>(ns, 1) * sizeof(float));
+    L.rsrc = cv.take(3 * std::max<size_t>(ns, 1) * sizeof(float));
     L.eptr = cv.take((size_t)(std::max(1, s->cnt.n_elem) + 1) * sizeof(int));
     L.epts = cv.take(std::max<size_t>(ns, 1) * sizeof(int));
     L.partials = cv.take((size_t)adj_objective_blocks(s->g) * sizeof(double));
@@ -1728,11 +1728,9 @@ int kw_adjoint_create(kw_sim *s, const float *weights, int32_t n_steps, void *de
         a.ub[i] = F(1 + i);
         a.rb[i] = F(4 + i);
         a.d[i] = F(7 + i);
-        a.T[i] = F(10 + i);
     }
-    a.pf = F(13);
-    a.w = F(14);
-    a.rbt = F(15);
+    a.w = F(10);
+    a.rbt = F(11);
     a.dJds = reinterpret_cast<double *>(ws + L.dJds);
     a.obj = reinterpret_cast<double *>(ws + L.obj);
     a.n_steps = n_steps;
@@ -1741,8 +1739,8 @@ int kw_adjoint_create(kw_sim *s, const float *weights, int32_t n_steps, void *de
     a.src_flat = reinterpret_cast<int *>(ws + L.flat);
     a.src_elem = reinterpret_cast<int *>(ws + L.elem);
     a.src_coef = reinterpret_cast<float *>(ws + L.coef);
-    a.corr = reinterpret_cast<float *>(ws + L.corr);
-    a.share = reinterpret_cast<double *>(ws + L.share);
+    a.add = reinterpret_cast<float *>(ws + L.add);
+    a.rsrc = reinterpret_cast<float *>(ws + L.rsrc);
     a.elem_ptr = reinterpret_cast<int *>(ws + L.eptr);
     a.elem_pts = reinterpret_cast<int *>(ws + L.epts);
     a.partials = reinterpret_cast<double *>(ws + L.partials);
@@ -1823,17 +1821,33 @@ int reverse_step(kw_adj *adj, int n, const char *rec) {
         }
         p_spec = s->buf.S[0];
     }
+    // x-row passes around the y and z passes of the transposed operators,
+    // through the spectral scratch S1..S6 (S0, the pressure state, is left alone)
     const bool loss = n + 1 >= s->record_start;
-    if (loss) KW_A(launch_xinv(st, g, s->cfg, s->tab, p_spec, a.pf, 1.0f / (float)s->grid.nx));
-    KW_A(launch_adj_eos(st, g, m, a, loss));
-    if (m.absorbing) KW_A(spectral(s, ZM_ABS, a.T, a.T, 2));
-    KW_A(launch_adj_src(st, g, m, a, s->src, n));
-    KW_A(launch_adj_den(st, g, s->tab, m, a));
-    KW_A(launch_adj_src_fix(st, a, m));
-    KW_A(spectral(s, ZM_DIVT, a.d, a.T, 3));
-    KW_A(launch_adj_vel(st, g, s->tab, m, a));
-    KW_A(spectral(s, ZM_GRADT, a.T, a.T, 3));
-    KW_A(launch_adj_sum(st, g, a));
+    const LaunchCfg &c = s->cfg;
+    const Tables &t = s->tab;
+    float2 *const *S = s->buf.S;
+    float2 *s12[2] = {S[1], S[2]}, *s45[2] = {S[4], S[5]};
+    float2 *s123[3] = {S[1], S[2], S[3]}, *s456[3] = {S[4], S[5], S[6]};
+    auto yzy = [&](int mode, float2 *const *in, float2 *const *out, int k) -> hipError_t {
+        hipError_t r = launch_ypass(st, g, c, t, in, k, false, nullptr, nullptr);
+        if (r == hipSuccess) r = launch_zfused(st, g, c, t, mode, in, out);
+        if (r == hipSuccess) r = launch_ypass(st, g, c, t, out, k, true, nullptr, nullptr);
+        return r;
+    };
+    KW_A(launch_adj_src(st, a, s->src, n));
+    if (m.absorbing) {
+        KW_A(launch_adjx(st, ADJX_EOS, g, c, t, m, s->src, a, p_spec, loss, nullptr, s12));
+        KW_A(yzy(ZM_ABS, s12, s45, 2));
+        KW_A(launch_adjx(st, ADJX_DEN_ABS, g, c, t, m, s->src, a, p_spec, loss, s45, s123));
+    } else {
+        KW_A(launch_adjx(st, ADJX_DEN, g, c, t, m, s->src, a, p_spec, loss, nullptr, s123));
+    }
+    KW_A(launch_adj_src_sum(st, a, n));
+    KW_A(yzy(ZM_DIVT, s123, s456, 3));
+    KW_A(launch_adjx(st, ADJX_VEL, g, c, t, m, s->src, a, nullptr, false, s456, s123));
+    KW_A(yzy(ZM_GRADT, s123, s456, 3));
+    KW_A(launch_adjx(st, ADJX_SUM, g, c, t, m, s->src, a, nullptr, false, s456, nullptr));
 #undef KW_A
     return KW_OK;
 }

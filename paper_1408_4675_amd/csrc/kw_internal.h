@@ -203,8 +203,6 @@ struct AdjDev {
                              // it is recomputed rather than read from a step record)
     const float *dfw[3];     // forward divergence d_xi of the step being reversed
     const float *rho[3];     // forward rho_xi after that step
-    float *T[3];             // temporaries
-    float *pf;               // p^(n+1)
     float *w;                // 2 w / (rho0 c0 N_w): derivative of the objective
     float *rbt;              // adjoint of rho (the sum of the components)
     double *dJds;            // [n_steps][n_elements] derivative by the drive values
@@ -214,8 +212,8 @@ struct AdjDev {
     const int *src_flat;     // flat index, element and coefficient of each point
     const int *src_elem;
     const float *src_coef;
-    float *corr;             // [3][n_src] source correction of the divergence adjoint
-    double *share;           // [n_src] share of each source point in dJ/ds_e(n)
+    float *add;              // [n_src] drive term coef_k s_e(n) of each point in this step
+    float *rsrc;             // [3][n_src] R_xi at each source point (see kw_adjx_den)
     const int *elem_ptr;     // [n_elem + 1] CSR of the points of each element
     const int *elem_pts;     // point numbers (k) of the elements, element by element
     double *partials;        // per-block partial sums of the objective
@@ -249,16 +247,16 @@ hipError_t launch_xinv(hipStream_t s, const GridDev &g, const LaunchCfg &c, cons
 // reverse-mode step pieces (kernels_adj.hip)
 hipError_t launch_adj_weights(hipStream_t s, const GridDev &g, const Medium &m, float *w,
                               float scale);
-hipError_t launch_adj_eos(hipStream_t s, const GridDev &g, const Medium &m, const AdjDev &a,
-                          bool loss);
-hipError_t launch_adj_src(hipStream_t s, const GridDev &g, const Medium &m, const AdjDev &a,
-                          const SourceDev &src, int n);
-hipError_t launch_adj_den(hipStream_t s, const GridDev &g, const Tables &t, const Medium &m,
-                          const AdjDev &a);
-hipError_t launch_adj_src_fix(hipStream_t s, const AdjDev &a, const Medium &m);
-hipError_t launch_adj_vel(hipStream_t s, const GridDev &g, const Tables &t, const Medium &m,
-                          const AdjDev &a);
-hipError_t launch_adj_sum(hipStream_t s, const GridDev &g, const AdjDev &a);
+// drive terms of the source points (before the den pass) and the per-element
+// sums of their shares into dJ/ds_e(n) (after it)
+hipError_t launch_adj_src(hipStream_t s, const AdjDev &a, const SourceDev &src, int n);
+hipError_t launch_adj_src_sum(hipStream_t s, const AdjDev &a, int n);
+// fused x-row passes of the reverse step (kw_adjx_*): p_spec and loss for the
+// eos and lossless den passes; Sin / Sout the spectra they read and write
+enum { ADJX_EOS = 0, ADJX_DEN = 1, ADJX_DEN_ABS = 2, ADJX_VEL = 3, ADJX_SUM = 4 };
+hipError_t launch_adjx(hipStream_t s, int pass, const GridDev &g, const LaunchCfg &c,
+                       const Tables &t, const Medium &m, const SourceDev &src, const AdjDev &ad,
+                       const float2 *p_spec, bool loss, float2 *const *Sin, float2 *const *Sout);
 // objective J into *out through per-block partials (adj_objective_blocks of them)
 int adj_objective_blocks(const GridDev &g);
 hipError_t launch_adj_objective(hipStream_t s, const GridDev &g, const float *w,

@@ -97,16 +97,15 @@ hipError_t launch_xinv(hipStream_t, const GridDev &, const LaunchCfg &, const Ta
 hipError_t launch_adj_weights(hipStream_t, const GridDev &, const Medium &, float *, float) {
     return launch_status();
 }
-hipError_t launch_adj_eos(hipStream_t, const GridDev &, const Medium &, const AdjDev &,
-                          bool) { return launch_status(); }
-hipError_t launch_adj_src(hipStream_t, const GridDev &, const Medium &, const AdjDev &,
-                          const SourceDev &, int) { return launch_status(); }
-hipError_t launch_adj_den(hipStream_t, const GridDev &, const Tables &, const Medium &,
-                          const AdjDev &) { return launch_status(); }
-hipError_t launch_adj_src_fix(hipStream_t, const AdjDev &, const Medium &) { return launch_status(); }
-hipError_t launch_adj_vel(hipStream_t, const GridDev &, const Tables &, const Medium &,
-                          const AdjDev &) { return launch_status(); }
-hipError_t launch_adj_sum(hipStream_t, const GridDev &, const AdjDev &) { return launch_status(); }
+hipError_t launch_adj_src(hipStream_t, const AdjDev &, const SourceDev &, int) {
+    return launch_status();
+}
+hipError_t launch_adj_src_sum(hipStream_t, const AdjDev &, int) { return launch_status(); }
+hipError_t launch_adjx(hipStream_t, int, const GridDev &, const LaunchCfg &, const Tables &,
+                       const Medium &, const SourceDev &, const AdjDev &, const float2 *, bool,
+                       float2 *const *, float2 *const *) {
+    return launch_status();
+}
 int adj_objective_blocks(const GridDev &g) {
     return (int)std::min<size_t>(((size_t)g.nx * g.rows + 255) / 256, 65535u * 8u);
 }
