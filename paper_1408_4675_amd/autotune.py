@@ -117,6 +117,14 @@ def candidates(axis: int, n: int) -> List[Tuple[List[int], int]]:
         scheds = _factorisations(n, (16, 15, 12, 10, 8, 6, 5, 4, 3, 2), 3)
         mn = min(len(s) for s in scheds)
         scheds = [s for s in scheds if len(s) == mn][:6]
+        # the mixed-radix fixed engine (12 or 20 elements per thread): the
+        # shortest schedules of radices that divide its width
+        for w in (12, 20):
+            if n % w == 0:
+                mixed = _factorisations(n, [q for q in (20, 12, 10, 6, 5, 4, 3, 2) if w % q == 0], 4)
+                if mixed:
+                    mnm = min(len(s) for s in mixed)
+                    scheds += [s for s in mixed if len(s) == mnm and s not in scheds][:3]
     tiles = (0, 4, 8, 16, 32) if axis == 0 else (0, 8, 16, 32)
     return [(s, t) for s, t in itertools.product(scheds, tiles)]
 

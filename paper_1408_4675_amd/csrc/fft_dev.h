@@ -339,12 +339,16 @@ __device__ __forceinline__ void fft_run(const FftPlan &P, const float2 *__restri
 }
 
 
-// --- fixed-width engine for power-of-two lengths -------------------------------
+// --- fixed-width engine ---------------------------------------------------------
 // Every thread owns E elements: x[t + m L], m < E, with L = n / E threads per
 // transform, in the first pass and after the last pass whatever the radix
 // schedule (every radix divides E).  A pass of radix R runs E/R butterflies per
 // thread, j = t + b L (b < E/R); butterfly j reads x[j + r n/R], which is
 // element t + L (b + r E/R) -- register b + r E/R.
+// E = 4, 8, 16 serve power-of-two lengths (radices 2, 4, 8, 16); E = 12 and
+// E = 20 serve lengths with a factor 3 or 5 (radices 2, 3, 4, 6, 12 and
+// 2, 4, 5, 10, 20), where the butterfly's position k = j mod Ns within its
+// group is no longer a bit mask.
 template <int E, int R, bool INV, int Bi>
 struct FixedBfly {
     template <class Lds>
@@ -354,7 +358,7 @@ struct FixedBfly {
         constexpr int B = E / R;
         if constexpr (Bi < B) {
             const int j = t + Bi * L;
-            const int k = j & (Ns - 1);
+            const int k = ((E & (E - 1)) == 0) ? (j & (Ns - 1)) : (int)((unsigned)j % (unsigned)Ns);
             if (Ns > 1) {
                 const int kst = __umul24(k, st);
 #pragma unroll
@@ -397,13 +401,19 @@ __device__ __forceinline__ void fft_fixed(const FftPlan &P, const float2 *__rest
         }
         const int st = P.n / (Ns * R);
         const bool write = p < P.np - 1;
+        // (a plan holds only radices that divide E)
         switch (R) {
         case 2: pass_fixed<E, 2, INV>(v, t, L, Ns, st, tw, lds, write); break;
-        case 4: pass_fixed<E, 4, INV>(v, t, L, Ns, st, tw, lds, write); break;
-        case 8: pass_fixed<E, 8, INV>(v, t, L, Ns, st, tw, lds, write); break;
-        default:
-            if constexpr (E >= 16) pass_fixed<E, 16, INV>(v, t, L, Ns, st, tw, lds, write);
-            break;
+        case 4: if constexpr (E % 4 == 0) pass_fixed<E, 4, INV>(v, t, L, Ns, st, tw, lds, write); break;
+        case 8: if constexpr (E % 8 == 0) pass_fixed<E, 8, INV>(v, t, L, Ns, st, tw, lds, write); break;
+        case 16: if constexpr (E % 16 == 0) pass_fixed<E, 16, INV>(v, t, L, Ns, st, tw, lds, write); break;
+        case 3: if constexpr (E % 3 == 0) pass_fixed<E, 3, INV>(v, t, L, Ns, st, tw, lds, write); break;
+        case 6: if constexpr (E % 6 == 0) pass_fixed<E, 6, INV>(v, t, L, Ns, st, tw, lds, write); break;
+        case 12: if constexpr (E % 12 == 0) pass_fixed<E, 12, INV>(v, t, L, Ns, st, tw, lds, write); break;
+        case 5: if constexpr (E % 5 == 0) pass_fixed<E, 5, INV>(v, t, L, Ns, st, tw, lds, write); break;
+        case 10: if constexpr (E % 10 == 0) pass_fixed<E, 10, INV>(v, t, L, Ns, st, tw, lds, write); break;
+        case 20: if constexpr (E % 20 == 0) pass_fixed<E, 20, INV>(v, t, L, Ns, st, tw, lds, write); break;
+        default: break;
         }
         Ns *= R;
     }

@@ -532,7 +532,7 @@ __global__ void __launch_bounds__(MAXT) kw_zfused(ZArgs a) {
     // one XCD (xcd_order): the second and third reads of the tile hit that
     // XCD's L2.  The merged absorption (ABSM) block transforms both inputs and
     // writes one output.
-    constexpr bool fused_grad = MODE == ZM_GRAD && Eng::fixed && !SPLIT;
+    constexpr bool fused_grad = MODE == ZM_GRAD && Eng::fixed && Eng::E <= 16 && !SPLIT;
     constexpr int R = (MODE == ZM_GRAD && !fused_grad) ? 3 : 1;
     int blk, o;
     if (!xcd_order(blockIdx.x, line_group(a.tb), R, a.ntiles * a.g.ny, blk, o)) return;
@@ -1291,12 +1291,14 @@ __global__ void __launch_bounds__(512) kw_xden3(XArgs a) {
 // MERGED: one input spectrum that already holds ta a + tb b (merged absorption
 // pass of a medium with scalar ta, tb) instead of a and b.
 // Asked to fit six wavefronts per SIMD (80 registers; a few bytes spill):
-// measured faster than five without spills.
+// measured faster than five without spills.  The 12- and 20-wide engines
+// would spill hundreds of bytes at 80 registers: no request for them.
 // The sensor and pressure-source lines alias the FFT row buffers (nx floats a
 // row fit in a buffer of row_pitch(M) complex values): they are used only
 // between the inverse transforms and the forward one, behind block barriers.
 template <class Eng, bool SENS, bool MERGED>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6))) kw_xeos(XArgs a) {
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((Eng::E == 12 || Eng::E == 20) ? 1 : 6)))
+kw_xeos(XArgs a) {
     KW_XPROLOGUE
     float *line = reinterpret_cast<float *>(sh);
     float2 va[E], v[E];
@@ -1365,6 +1367,8 @@ __global__ void __launch_bounds__(512) kw_xinv(XArgs a) {
     case ENG_G32: { using Eng = EngGeneric<32>; BODY; } break;                 \
     case ENG_F4:  { using Eng = EngFixed<4>; BODY; } break;                    \
     case ENG_F8:  { using Eng = EngFixed<8>; BODY; } break;                    \
+    case ENG_F12: { using Eng = EngFixed<12>; BODY; } break;                   \
+    case ENG_F20: { using Eng = EngFixed<20>; BODY; } break;                   \
     default:      { using Eng = EngFixed<16>; BODY; } break;                   \
     }
 

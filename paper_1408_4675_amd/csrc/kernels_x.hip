@@ -75,8 +75,9 @@ hipError_t launch_xden(hipStream_t s, const GridDev &g, const LaunchCfg &c, cons
     a.Sout[0] = Sout[0];
     a.Sout[1] = Sout[1];
     a.rho_total = rho_total;
-    if (c.eng_x == ENG_G16 || c.eng_x == ENG_G32) {
-        // generic engines: three thread groups per row (see kw_xden3)
+    if (c.eng_x == ENG_G16 || c.eng_x == ENG_G32 || c.eng_x == ENG_F12 || c.eng_x == ENG_F20) {
+        // generic and mixed-radix engines: three thread groups per row (see
+        // kw_xden3; their wider register arrays leave no room for the sums)
         a.tb = c.tb_den;
         dim3 grid((g.rows + c.tb_den - 1) / c.tb_den);
         dim3 block(3 * c.tb_den * c.px.L);
@@ -87,6 +88,8 @@ hipError_t launch_xden(hipStream_t s, const GridDev &g, const LaunchCfg &c, cons
         else hipLaunchKernelGGL((kw_xden3<ENGT, false>), grid, block, lds, s, a);                  \
     } while (0)
         if (c.eng_x == ENG_G16) KW_DEN3(EngGeneric<16>);
+        else if (c.eng_x == ENG_F12) KW_DEN3(EngFixed<12>);
+        else if (c.eng_x == ENG_F20) KW_DEN3(EngFixed<20>);
         else KW_DEN3(EngGeneric<32>);
 #undef KW_DEN3
         return hipGetLastError();

@@ -93,7 +93,7 @@ hipError_t launch_zfused(hipStream_t s, const GridDev &g, const LaunchCfg &c, co
     // outputs in one block, except on long columns (blocks of 512 threads or
     // more), where the kept spectrum would leave one block per CU: there it
     // runs one block per output (split), like the generic engines.
-    const bool split = mode == ZM_GRAD && (!fixed_z || a.tb * c.pz.L >= 512);
+    const bool split = mode == ZM_GRAD && (!fixed_z || c.eng_z == ENG_F20 || a.tb * c.pz.L >= 512);
     // one block per tile and output, in XCD-aware order (xcd_order): the
     // gradient's blocks (one, or three when split) in a 1D grid, the other
     // modes' outputs along blockIdx.y

@@ -136,8 +136,10 @@ struct StepBuffers {
 // FFT engines: generic one-butterfly-per-thread Stockham with register arrays
 // of 16 or 32 (any 2^a 3^b 5^c length), or the fixed-width engine with 8 or 16
 // elements per thread (power-of-two lengths, radices 2/4/8/16).
-enum EngId { ENG_G16 = 0, ENG_G32 = 1, ENG_F8 = 2, ENG_F16 = 3, ENG_F4 = 4 };
-inline bool eng_fixed(int e) { return e == ENG_F4 || e == ENG_F8 || e == ENG_F16; }
+enum EngId { ENG_G16 = 0, ENG_G32 = 1, ENG_F8 = 2, ENG_F16 = 3, ENG_F4 = 4, ENG_F12 = 5, ENG_F20 = 6 };
+inline bool eng_fixed(int e) {
+    return e == ENG_F4 || e == ENG_F8 || e == ENG_F16 || e == ENG_F12 || e == ENG_F20;
+}
 
 struct LaunchCfg {
     int eng_x, eng_y, eng_z; // EngId per axis

@@ -370,6 +370,28 @@ def test_parity_constant_rho0_absorbing(kw, shape):
         assert e <= tol, (k, e)
 
 
+# Lengths 2^a 3 and 2^a 5 on the mixed-radix fixed engine (12 or 20 elements
+# per thread, radices dividing 12 or 20, butterfly groups of non-power-of-two
+# size): x rows of 24, 40 and 48 points (density pass in three thread groups),
+# y and z columns of 24 to 100 points, next to generic-engine axes.
+MIXED = [((48, 40, 36), [(0, [12, 2]), (1, [20, 2]), (2, [12, 3])]),
+         ((80, 24, 60), [(0, [20, 2]), (1, [12, 2])]),
+         ((96, 36, 40), [(0, [12, 4]), (1, [6, 6]), (2, [10, 4])]),
+         ((40, 48, 100), [(1, [4, 4, 3]), (2, [20, 5])])]
+
+
+@pytest.mark.parametrize("shape,plans", MIXED, ids=["%dx%dx%d" % c[0] for c in MIXED])
+def test_parity_mixed_radix_engine(kw, shape, plans):
+    nx, ny, nz = shape
+    scen = sc.small_case(nx, ny, nz, seed=21, heterogeneous=True, nonlinear=True, absorbing=True,
+                         pml=3, steps=12, sensor_mask=True, amp=2e6)
+    scen = scen.replace(name="mixed_" + scen.name)
+    sim, orc = _run_both(kw, scen, 12, plans=plans)
+    errs, tol = compare_outputs(sim, orc, scen, REPORT)
+    for k, e in errs.items():
+        assert e <= tol, (k, e)
+
+
 @pytest.mark.slow
 def test_water_bowl_1024_full_size_properties(kw):
     """The 1024^3 homogeneous water grid with the 3 MHz bowl, in the launch
