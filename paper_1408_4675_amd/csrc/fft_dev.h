@@ -288,7 +288,6 @@ struct RowLds {
 };
 // Whether the rows of L threads of a block lie within wavefronts
 __device__ __forceinline__ bool rows_in_waves(int L) { return (warpSize % L) == 0; }
-__host__ __device__ inline int row_pitch(int n) { return n + (n >> 4) + 1; }
 
 // --- the pass loop -----------------------------------------------------------
 // On entry v[r] (r < radix[0]) holds x[t + r n/radix[0]] for t < n/radix[0].

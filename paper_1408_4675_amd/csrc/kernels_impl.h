@@ -672,19 +672,30 @@ __device__ __forceinline__ void row_c2r(const XArgs &a, const float2 *S, int b, 
         const uint32_t l1 = (uint32_t)(b * M + t) * 8u;
         const uint32_t l2 = (uint32_t)(b * M + step - t) * 8u;
         const float2 *const row = S + ((size_t)blockIdx.x * a.tb + b) * M;
+        // every load first, then the arithmetic: with the k = 0 case as a
+        // branch between the loads each element waited for its own loads
+        // (k = 0 reads an element of its own row in place of M - k, unused)
+        float2 P[E], Q[E];
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             if (m < cin) {
                 const int k = Eng::in_index(a.pi, t, m);
-                const float2 P = UB ? ld_at(blk + m * step, l1) : row[k];
-                float2 xk, xm;
-                if (k == 0) {
-                    xk = make_float2(P.x, 0.0f);
-                    xm = make_float2(P.y, 0.0f);
+                if (UB) {
+                    P[m] = ld_at(blk + m * step, l1);
+                    Q[m] = ld_at(blk + M - (m + 1) * step, (m == 0 && t == 0) ? l2 - (uint32_t)step * 8u : l2);
                 } else {
-                    xk = P;
-                    xm = UB ? ld_at(blk + M - (m + 1) * step, l2) : row[M - k];
+                    P[m] = row[k];
+                    Q[m] = row[k == 0 ? 0 : M - k];
                 }
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            if (m < cin) {
+                const int k = Eng::in_index(a.pi, t, m);
+                const bool k0 = k == 0;
+                const float2 xk = k0 ? make_float2(P[m].x, 0.0f) : P[m];
+                const float2 xm = k0 ? make_float2(P[m].y, 0.0f) : Q[m];
                 const float2 A = make_float2(xk.x + xm.x, xk.y - xm.y);        // xk + conj(xm)
                 const float2 D = make_float2(xk.x - xm.x, xk.y + xm.y);        // xk - conj(xm)
                 const float2 B = c_mulc(D, tw_post[k]);                         // * w^-k

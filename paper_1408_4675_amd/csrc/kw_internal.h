@@ -163,8 +163,11 @@ inline bool den_needs_line(const Medium &m, const SourceDev &src, const SensorDe
            (!m.absorbing && ((sen.row_ptr != nullptr && !sen.all_points) ||
                              (src.row_ptr != nullptr && src.kind == KW_SOURCE_PRESSURE)));
 }
+// LDS pitch (complex values) of a row buffer of the x passes: n values plus
+// one pad slot per 16 (see RowLds)
+__host__ __device__ inline int row_pitch(int n) { return n + (n >> 4) + 1; }
 inline size_t den_lds_bytes(int M, int nx, int tb, bool line) {
-    const size_t rp = (size_t)M + (M >> 4) + 1;
+    const size_t rp = (size_t)row_pitch(M);
     return (size_t)3 * tb * rp * 8 + (size_t)tb * M * 8 +
            (line ? (size_t)tb * nx * 4 : 0);
 }
@@ -172,7 +175,7 @@ inline size_t den_lds_bytes(int M, int nx, int tb, bool line) {
 // optionally a line of nx floats per row), of the y pass and of the z pass
 // (twiddle table and the column tile)
 inline size_t x_lds_bytes(int M, int nx, int tb, bool line) {
-    const size_t rp = (size_t)M + (M >> 4) + 1;
+    const size_t rp = (size_t)row_pitch(M);
     return (size_t)2 * M * 8 + (size_t)tb * rp * 8 + (line ? (size_t)tb * nx * 4 : 0);
 }
 inline size_t col_lds_bytes(int n, int tb) { return (size_t)n * 8 + (size_t)tb * n * 8; }
