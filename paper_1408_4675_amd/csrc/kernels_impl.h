@@ -806,6 +806,39 @@ __global__ void __launch_bounds__(512) kw_xvel(XArgs a) {
     const int iy = rr % a.g.ny, iz = rr / a.g.ny;
     const int xi = blockIdx.y;
     float2 v[E];
+    // u, Delta t / rho0+ and the PML factors of the update are loaded before
+    // the transform (independent of it): issued one element at a time between
+    // the stores of the update, each waited for its own memory round trip.
+    // Fixed engines up to 12 elements a thread: measured faster at 256^3,
+    // 192^3 and 1024^3; the generic engines' register arrays went from five to
+    // two wavefronts per SIMD with it (160^3 velocity pass 76 -> 100 us).
+    constexpr bool PRE = Eng::fixed && Eng::E <= 12;
+    float2 u0v[E], dv[E], qv[E];
+    if constexpr (PRE) {
+        float *u = pick3(a.fld, xi);
+        const Coef dtr = xi == 0 ? a.m.dtr[0] : xi == 1 ? a.m.dtr[1] : a.m.dtr[2];
+        const float qy = a.t.pml_sy[iy], qz = a.t.pml_sz[iz];
+        if (ok) {
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                if (m < cupd) {
+                    const int x = 2 * Eng::out_index(a.pi, t, m);
+                    const XPos i{xrow0 + 2 * (size_t)m * Eng::out_step(a.pi), xlane};
+                    u0v[m] = ld2(u, i);
+                    if (xi == 0) qv[m] = *reinterpret_cast<const float2 *>(a.t.pml_sx + x);
+                    else qv[m] = xi == 1 ? make_float2(qy, qy) : make_float2(qz, qz);
+                }
+            }
+            if (dtr.map) {
+#pragma unroll
+                for (int m = 0; m < E; ++m)
+                    if (m < cupd) dv[m] = ld2(dtr.map, XPos{xrow0 + 2 * (size_t)m * Eng::out_step(a.pi), xlane});
+            } else {
+#pragma unroll
+                for (int m = 0; m < E; ++m) dv[m] = make_float2(dtr.scalar, dtr.scalar);
+            }
+        }
+    }
     row_c2r<Eng>(a, pick3(a.Sin, xi), b, ok, t, lds, v, tws, tws + M);
     // force source on this component: dt F per point in the LDS line
     float *const fline = reinterpret_cast<float *>(sh + (size_t)a.tb * row_pitch(M)) + (size_t)b * nx;
@@ -824,12 +857,17 @@ __global__ void __launch_bounds__(512) kw_xvel(XArgs a) {
             if (m < cupd) {
                 const int x = 2 * Eng::out_index(a.pi, t, m);
                 const XPos i{xrow0 + 2 * (size_t)m * Eng::out_step(a.pi), xlane};
-                float2 q;
-                if (xi == 0) q = make_float2(a.t.pml_sx[x], a.t.pml_sx[x + 1]);
-                else if (xi == 1) q = make_float2(qy, qy);
-                else q = make_float2(qz, qz);
-                const float2 d = coef2_at(dtr, i);
-                const float2 u0 = ld2(u, i);
+                float2 q, d, u0;
+                if constexpr (PRE) {
+                    q = qv[m];
+                    d = dv[m];
+                    u0 = u0v[m];
+                } else {
+                    if (xi == 0) q = make_float2(a.t.pml_sx[x], a.t.pml_sx[x + 1]);
+                    else q = xi == 1 ? make_float2(qy, qy) : make_float2(qz, qz);
+                    d = coef2_at(dtr, i);
+                    u0 = ld2(u, i);
+                }
                 const float2 g = v[m];
                 float2 un;
                 un.x = q.x * (q.x * u0.x - d.x * g.x);
@@ -960,6 +998,33 @@ __device__ __forceinline__ void finish_pressure(const XArgs &a, float *line, int
         }
     }
     bool bad = false;
+    if (ok && rec && a.sen.all_points) {
+        // each accumulator: every element's load, then every store (stored one
+        // element at a time between the loads, each element waited for its
+        // own load: the stores might alias the next loads)
+        if (a.sen.p_max) {
+            float2 acc[E];
+#pragma unroll
+            for (int m = 0; m < E; ++m)
+                if (m < cnt) acc[m] = ld2(a.sen.p_max, XPos{xrow0 + 2 * (size_t)m * Eng::out_step(a.pi), xlane});
+#pragma unroll
+            for (int m = 0; m < E; ++m)
+                if (m < cnt)
+                    st2(a.sen.p_max, XPos{xrow0 + 2 * (size_t)m * Eng::out_step(a.pi), xlane},
+                        make_float2(fmaxf(acc[m].x, v[m].x), fmaxf(acc[m].y, v[m].y)));
+        }
+        if (a.sen.p_sum2) {
+            float2 acc[E];
+#pragma unroll
+            for (int m = 0; m < E; ++m)
+                if (m < cnt) acc[m] = ld2(a.sen.p_sum2, XPos{xrow0 + 2 * (size_t)m * Eng::out_step(a.pi), xlane});
+#pragma unroll
+            for (int m = 0; m < E; ++m)
+                if (m < cnt)
+                    st2(a.sen.p_sum2, XPos{xrow0 + 2 * (size_t)m * Eng::out_step(a.pi), xlane},
+                        make_float2(acc[m].x + v[m].x * v[m].x, acc[m].y + v[m].y * v[m].y));
+        }
+    }
     if (ok) {
 #pragma unroll
         for (int m = 0; m < E; ++m) {
@@ -968,14 +1033,6 @@ __device__ __forceinline__ void finish_pressure(const XArgs &a, float *line, int
                 bad |= !(__builtin_isfinite(p.x) && __builtin_isfinite(p.y));
                 if (rec && a.sen.all_points) {
                     const XPos i{xrow0 + 2 * (size_t)m * Eng::out_step(a.pi), xlane};
-                    if (a.sen.p_max) {
-                        const float2 mx = ld2(a.sen.p_max, i);
-                        st2(a.sen.p_max, i, make_float2(fmaxf(mx.x, p.x), fmaxf(mx.y, p.y)));
-                    }
-                    if (a.sen.p_sum2) {
-                        const float2 s = ld2(a.sen.p_sum2, i);
-                        st2(a.sen.p_sum2, i, make_float2(s.x + p.x * p.x, s.y + p.y * p.y));
-                    }
                     if constexpr (SENS) {
                         if (a.sen.p_min) {
                             const float2 mn = ld2(a.sen.p_min, i);
@@ -1065,6 +1122,16 @@ __global__ void __launch_bounds__(512) kw_xden(XArgs a) {
         float2 v[E];
         row_c2r<Eng>(a, pick3(a.Sin, g), b, ok, ts, ldg, v, tws, tws + M, salt);
         float *rho = pick3(a.fld, g);
+        // rho_xi of every element loaded before the updates (between the
+        // stores of the previous elements each load waited for itself)
+        float2 oldv[E];
+        if (ok) {
+#pragma unroll
+            for (int m = 0; m < E; ++m)
+                if (m < cupd)
+                    oldv[m] = ld2(rho, XPos{xrow0 + 2 * (size_t)m * (Eng::out_step(a.pi) + salt),
+                                            (uint32_t)(b * nx + 2 * ts) * 4u});
+        }
         if (ok) {
 #pragma unroll
             for (int m = 0; m < E; ++m) {
@@ -1085,7 +1152,7 @@ __global__ void __launch_bounds__(512) kw_xden(XArgs a) {
                     } else {
                         r0 = *reinterpret_cast<const float2 *>(r0l + x);
                     }
-                    const float2 old = ld2(rho, i);
+                    const float2 old = oldv[m];
                     const float2 d = v[m];
                     float2 nw;
                     nw.x = q.x * (q.x * old.x - dt * r0.x * d.x);
@@ -1212,6 +1279,17 @@ __global__ void __launch_bounds__(512) kw_xden3(XArgs a) {
         float *rho = pick3(a.fld, g);
         const float qy = a.t.pml_y[iy], qz = a.t.pml_z[iz];
         float2 *xrho = (g == 0) ? buf0 : buf2;
+        // rho_g of every element loaded before the updates (between the
+        // stores of the previous elements each load waited for itself); the
+        // fixed engines only (measured: 192^3 density pass 155 -> 152 us, the
+        // generic engine's 160^3 one 86 -> 93 us for a wavefront less)
+        constexpr bool PRE = Eng::fixed;
+        float2 oldv[E];
+        if (PRE && ok) {
+#pragma unroll
+            for (int m = 0; m < E; ++m)
+                if (m < cupd) oldv[m] = ld2(rho, rbase + 2 * Eng::out_index(a.pi, t, m));
+        }
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             if (m < cupd) {
@@ -1226,7 +1304,7 @@ __global__ void __launch_bounds__(512) kw_xden3(XArgs a) {
                     else if (g == 1) q = make_float2(qy, qy);
                     else q = make_float2(qz, qz);
                     const float2 r0 = coef2_at(a.m.rho0, i);
-                    const float2 old = ld2(rho, i);
+                    const float2 old = PRE ? oldv[m] : ld2(rho, i);
                     nw.x = q.x * (q.x * old.x - dt * r0.x * d.x);
                     nw.y = q.y * (q.y * old.y - dt * r0.y * d.y);
                     if (a.m.nonlinear) {
@@ -1302,13 +1380,13 @@ __global__ void __launch_bounds__(512) kw_xden3(XArgs a) {
 // MERGED: one input spectrum that already holds ta a + tb b (merged absorption
 // pass of a medium with scalar ta, tb) instead of a and b.
 // Asked to fit six wavefronts per SIMD (80 registers; a few bytes spill):
-// measured faster than five without spills.  The 12- and 20-wide engines
-// would spill hundreds of bytes at 80 registers: no request for them.
+// measured faster than five without spills.  The wider engines would spill
+// hundreds of bytes at 80 registers: no request for them.
 // The sensor and pressure-source lines alias the FFT row buffers (nx floats a
 // row fit in a buffer of row_pitch(M) complex values): they are used only
 // between the inverse transforms and the forward one, behind block barriers.
 template <class Eng, bool SENS, bool MERGED>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((Eng::E == 12 || Eng::E == 20) ? 1 : 6)))
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((Eng::fixed && Eng::E <= 8) ? 6 : 1)))
 kw_xeos(XArgs a) {
     KW_XPROLOGUE
     float *line = reinterpret_cast<float *>(sh);
