@@ -33,19 +33,20 @@ def log(msg):
 
 
 def measured_traffic(kernel_class, npts):
-    """HBM bytes per launch of `kernel_class` from the committed rocprofv3 PMC
-    summary, if it was taken on the current kernel sources and on a grid of
-    `npts` points (the workload being reported); else None."""
-    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
-    if not os.path.exists(path):
-        return None
-    with open(path) as fh:
-        d = json.load(fh)
+    """HBM bytes per launch of `kernel_class` from a committed rocprofv3 PMC
+    summary (profiles/pmc_traffic*.json) taken on the current kernel sources
+    and on a grid of `npts` points (the workload being reported); else None."""
+    import glob
     from paper_1408_4675_amd.profiling import kernel_source_hash
-    if d.get("source_hash") != kernel_source_hash() or d.get("points") != npts:
-        return None
-    k = d.get("kernels", {}).get(kernel_class)
-    return None if k is None else k.get("hbm_bytes_per_launch")
+    h = kernel_source_hash()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "pmc_traffic*.json"))):
+        with open(path) as fh:
+            d = json.load(fh)
+        if d.get("source_hash") != h or d.get("points") != npts:
+            continue
+        k = d.get("kernels", {}).get(kernel_class)
+        return None if k is None else k.get("hbm_bytes_per_launch")
+    return None
 
 
 def time_workload(scen, steps, warmup):
