@@ -39,7 +39,9 @@ CSRC = os.path.join(HERE, "csrc")
 # kernel name fragment -> class name reported by kw_stats
 CLASS_OF = (("kw_ypass", None), ("kw_zfused", None), ("kw_xvel", "xvel"), ("kw_xden", "xden"),
             ("kw_xeos", "xeos"), ("kw_xfwd", "xfwd"), ("kw_xinv", "xinv"),
-            ("kw_finalize", "finalize"), ("kw_fill", "fill"))
+            ("kw_finalize", "finalize"), ("kw_fill", "fill"),
+            ("kw_adjx_eos", "adjx_eos"), ("kw_adjx_den", "adjx_den"), ("kw_adjx_vel", "adjx_vel"),
+            ("kw_adjx_sum", "adjx_sum"), ("kw_adj_src", "adj_src"), ("kw_adj_", "adj_setup"))
 
 
 def kernel_source_hash() -> str:
@@ -213,6 +215,18 @@ def run_workload(name: str, steps: int, warmup: int, eager: bool):
     import torch
     from . import scenarios as sc
     from .simulation import Simulation
+    if name == "adjoint_bowl_128":
+        # forward run with checkpoints every 50 steps, then the reverse sweep
+        from .adjoint import _Run
+        scen, focus = sc.adjoint_bowl(seed=0, steps=steps)
+        w = sc.focal_weights(scen.grid, focus, 2e-3)
+        r = _Run(scen, w, 50)
+        r.backward()
+        print("%s: %d steps, forward %.4f ms per step, reverse sweep %.4f ms per step" % (
+            name, steps, r.forward_s / steps * 1e3, r.backward_s / steps * 1e3), flush=True)
+        r.close()
+        torch.cuda.synchronize()
+        return
     if name.startswith("tissue_bowl_"):
         scen = sc.tissue_bowl(seed=0, n=int(name.split("_")[-1]), steps=steps)
     elif name == "water_bowl_1024":
