@@ -220,7 +220,7 @@ bool axis_plan(int n, int axis, const std::vector<int> *rad, int &eng, FftPlan &
             r = *rad;
             // the width is the largest radix of a caller-chosen schedule
             const int rm = *std::max_element(r.begin(), r.end());
-            E = rm > 8 ? 16 : rm > 4 ? 8 : 4;
+            E = rm > 16 ? 32 : rm > 8 ? 16 : rm > 4 ? 8 : 4;
         } else {
             int m = n;
             while (m > 1) {
@@ -231,7 +231,7 @@ bool axis_plan(int n, int axis, const std::vector<int> *rad, int &eng, FftPlan &
             }
         }
         if (fixed_plan_from_radices(n, E, r, f)) {
-            eng = E == 16 ? ENG_F16 : E == 8 ? ENG_F8 : ENG_F4;
+            eng = E == 32 ? ENG_F32 : E == 16 ? ENG_F16 : E == 8 ? ENG_F8 : ENG_F4;
             i = f;
             return true;
         }
@@ -742,10 +742,12 @@ int build_graph(kw_sim *s) {
 // A block of tb x L threads with `lds` bytes: up to 512 threads and 64 KB, or,
 // for the column passes of the fixed engines (`wide`), up to 1024 threads and
 // the device's LDS per block.
+// wide: 1024-thread instantiations exist (fixed 8- and 16-wide engines);
+// big_lds: the block may use all the LDS of a CU (fixed engines but 12, 20)
 int check_tb(const char *what, int tb, int L, size_t lds, bool wide = false,
-             size_t max_lds = 64 * 1024) {
+             size_t max_lds = 64 * 1024, bool big_lds = false) {
     const int max_threads = wide ? 1024 : 512;
-    const size_t lds_cap = wide ? max_lds : (size_t)64 * 1024;
+    const size_t lds_cap = (wide || big_lds) ? max_lds : (size_t)64 * 1024;
     if (tb < 1 || tb * L > max_threads)
         return fail(KW_EUNSUPPORTED, "%s: %d x %d threads exceed a block", what, tb, L);
     if (lds > lds_cap) return fail(KW_EUNSUPPORTED, "%s: %zu bytes of LDS", what, lds);
@@ -760,7 +762,7 @@ int pick_tiles(kw_sim *s, int tile_y, int tile_z) {
     while (c.tb_x > 1 && x_lds_bytes(g.M, g.nx, c.tb_x, true) > 64 * 1024) c.tb_x /= 2;
     // rows per block of the three-group density kernel of the generic
     // engines: as many as fit 512 threads and 64 KB of LDS
-    if (c.eng_x == ENG_G16 || c.eng_x == ENG_G32 || c.eng_x == ENG_F12 || c.eng_x == ENG_F20) {
+    if (!eng_fixed(c.eng_x) || c.eng_x == ENG_F12 || eng_wide(c.eng_x)) {
         const bool line = den_needs_line(s->med, s->src, s->sen);
         auto fits = [&](int tb) {
             return 3 * tb * c.px.L <= 512 && den_lds_bytes(g.M, g.nx, tb, line) <= 64 * 1024;
@@ -777,29 +779,49 @@ int pick_tiles(kw_sim *s, int tile_y, int tile_z) {
     // where a block can hold them -- for the fixed engines up to 1024 threads
     // and the device's LDS per block (measured at 1024^3: 120 -> 111 ms per
     // step against 8 columns of 512 threads), else 512 threads and 64 KB
-    auto col_tile = [&](int n, int L, int req, bool wide, size_t (*bytes)(int, int)) {
+    auto col_tile = [&](int n, int L, int req, bool wide, size_t (*bytes)(int, int), bool big = false) {
         if (req > 0) return req;
         const int max_threads = wide ? 1024 : 512;
-        const size_t max_bytes = wide ? s->max_lds : (size_t)64 * 1024;
+        const size_t max_bytes = (wide || big) ? s->max_lds : (size_t)64 * 1024;
         int tb = 16;
         while (tb > 1 && (tb * L > max_threads || bytes(n, tb) > max_bytes)) tb /= 2;
         return tb;
     };
-    c.tb_y = col_tile(g.ny, c.py.L, tile_y, c.eng_y == ENG_F8 || c.eng_y == ENG_F16, col_lds_bytes);
-    c.tb_z = col_tile(g.nz, c.pz.L, tile_z, c.eng_z == ENG_F8 || c.eng_z == ENG_F16, zcol_lds_bytes);
+    c.tb_y = col_tile(g.ny, c.py.L, tile_y, c.eng_y == ENG_F8 || c.eng_y == ENG_F16, col_lds_bytes,
+                      c.eng_y == ENG_F32);
+    c.tb_z = col_tile(g.nz, c.pz.L, tile_z, c.eng_z == ENG_F8 || c.eng_z == ENG_F16, zcol_lds_bytes,
+                      c.eng_z == ENG_F32);
     int rc;
     if ((rc = check_tb("x pass", c.tb_x, c.px.L, x_lds_bytes(g.M, g.nx, c.tb_x, true))) != KW_OK)
         return rc;
     const bool wide_y = c.eng_y == ENG_F8 || c.eng_y == ENG_F16;
     const bool wide_z = c.eng_z == ENG_F8 || c.eng_z == ENG_F16;
     if ((rc = check_tb("y pass", c.tb_y, c.py.L, col_lds_bytes(g.ny, c.tb_y), wide_y,
-                       s->max_lds)) != KW_OK)
+                       s->max_lds, c.eng_y == ENG_F32)) != KW_OK)
         return rc;
     if ((rc = check_tb("z pass", c.tb_z, c.pz.L, zcol_lds_bytes(g.nz, c.tb_z), wide_z,
-                       s->max_lds)) != KW_OK)
+                       s->max_lds, c.eng_z == ENG_F32)) != KW_OK)
         return rc;
+    // The merged absorption pass holds two spectra per thread and runs at two
+    // wavefronts per SIMD with either fixed engine; on 1024-point columns it
+    // takes the 32-wide engine's two radix-32 passes in 16-column tiles
+    // (measured at 1024^3: 11.5 -> 8.8 ms; the gradient and divergence passes,
+    // at four wavefronts on the 16-wide engine, lost with it)
+    c.eng_za = c.eng_z;
+    c.pza = c.pz;
+    c.pzai = c.pzi;
+    c.tb_za = c.tb_z;
+    if (g.nz == 1024 && c.eng_z == ENG_F16) {
+        FftPlan f;
+        if (fixed_plan_from_radices(1024, 32, {32, 32}, f) && 16 * f.L <= 512 &&
+            zcol_lds_bytes(g.nz, 16) <= s->max_lds) {
+            c.eng_za = ENG_F32;
+            c.pza = c.pzai = f;
+            c.tb_za = 16;
+        }
+    }
     // the column passes address an element of their tile by a 32-bit byte offset
-    const uint64_t zlane = ((uint64_t)c.pz.L * g.M * g.ny + c.tb_z) * 8;
+    const uint64_t zlane = ((uint64_t)std::max(c.pz.L, c.pza.L) * g.M * g.ny + std::max(c.tb_z, c.tb_za)) * 8;
     if (zlane >= (1ull << 32))
         return fail(KW_EUNSUPPORTED, "z pass: tile offsets of %llu bytes exceed 32 bits",
                     (unsigned long long)zlane);

@@ -344,7 +344,7 @@ __device__ __forceinline__ void fft_run(const FftPlan &P, const float2 *__restri
 // schedule (every radix divides E).  A pass of radix R runs E/R butterflies per
 // thread, j = t + b L (b < E/R); butterfly j reads x[j + r n/R], which is
 // element t + L (b + r E/R) -- register b + r E/R.
-// E = 4, 8, 16 serve power-of-two lengths (radices 2, 4, 8, 16); E = 12 and
+// E = 4, 8, 16, 32 serve power-of-two lengths (radices 2 to 32); E = 12 and
 // E = 20 serve lengths with a factor 3 or 5 (radices 2, 3, 4, 6, 12 and
 // 2, 4, 5, 10, 20), where the butterfly's position k = j mod Ns within its
 // group is no longer a bit mask.
@@ -406,6 +406,7 @@ __device__ __forceinline__ void fft_fixed(const FftPlan &P, const float2 *__rest
         case 4: if constexpr (E % 4 == 0) pass_fixed<E, 4, INV>(v, t, L, Ns, st, tw, lds, write); break;
         case 8: if constexpr (E % 8 == 0) pass_fixed<E, 8, INV>(v, t, L, Ns, st, tw, lds, write); break;
         case 16: if constexpr (E % 16 == 0) pass_fixed<E, 16, INV>(v, t, L, Ns, st, tw, lds, write); break;
+        case 32: if constexpr (E % 32 == 0) pass_fixed<E, 32, INV>(v, t, L, Ns, st, tw, lds, write); break;
         case 3: if constexpr (E % 3 == 0) pass_fixed<E, 3, INV>(v, t, L, Ns, st, tw, lds, write); break;
         case 6: if constexpr (E % 6 == 0) pass_fixed<E, 6, INV>(v, t, L, Ns, st, tw, lds, write); break;
         case 12: if constexpr (E % 12 == 0) pass_fixed<E, 12, INV>(v, t, L, Ns, st, tw, lds, write); break;

@@ -1283,7 +1283,7 @@ __global__ void __launch_bounds__(512) kw_xden3(XArgs a) {
         // stores of the previous elements each load waited for itself); the
         // fixed engines only (measured: 192^3 density pass 155 -> 152 us, the
         // generic engine's 160^3 one 86 -> 93 us for a wavefront less)
-        constexpr bool PRE = Eng::fixed;
+        constexpr bool PRE = Eng::fixed && Eng::E <= 12;
         float2 oldv[E];
         if (PRE && ok) {
 #pragma unroll
@@ -1458,6 +1458,7 @@ __global__ void __launch_bounds__(512) kw_xinv(XArgs a) {
     case ENG_F8:  { using Eng = EngFixed<8>; BODY; } break;                    \
     case ENG_F12: { using Eng = EngFixed<12>; BODY; } break;                   \
     case ENG_F20: { using Eng = EngFixed<20>; BODY; } break;                   \
+    case ENG_F32: { using Eng = EngFixed<32>; BODY; } break;                   \
     default:      { using Eng = EngFixed<16>; BODY; } break;                   \
     }
 

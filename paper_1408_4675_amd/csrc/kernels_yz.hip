@@ -82,8 +82,17 @@ hipError_t launch_zfused(hipStream_t s, const GridDev &g, const LaunchCfg &c, co
         a.add0[0] = add0[0];
         a.add0[1] = add0[1];
     }
-    const bool fixed_z = eng_fixed(c.eng_z);
-    if (mode == ZM_ABSM && a.tb * c.pz.L > 512 && a.tb > 1) {
+    int eng = c.eng_z;
+    if (mode == ZM_ABSM) {
+        // the merged absorption's own engine and plans (see LaunchCfg)
+        eng = c.eng_za;
+        a.pf = c.pza;
+        a.pi = c.pzai;
+        a.tb = c.tb_za;
+        a.ntiles = (g.M + a.tb - 1) / a.tb;
+    }
+    const bool fixed_z = eng_fixed(eng);
+    if (mode == ZM_ABSM && a.tb * a.pf.L > 512 && a.tb > 1) {
         // the merged absorption holds two spectra per thread: they do not fit
         // the registers of a 1024-thread block, so it runs half-width tiles
         a.tb /= 2;
@@ -95,12 +104,12 @@ hipError_t launch_zfused(hipStream_t s, const GridDev &g, const LaunchCfg &c, co
     // narrower tiles (1024 points: 4 columns, 256 threads) rather than one
     // block per output, which re-reads the input and transforms it three times
     // (measured at 1024^3: 9.8 ms against 11.0 ms).  The generic and the
-    // 20-wide engines run one block per output (split).
-    if (mode == ZM_GRAD && fixed_z && c.eng_z != ENG_F20) {
-        while (a.tb > 1 && a.tb * c.pz.L >= 512) a.tb /= 2;
+    // 20- and 32-wide engines run one block per output (split).
+    if (mode == ZM_GRAD && fixed_z && !eng_wide(eng)) {
+        while (a.tb > 1 && a.tb * a.pf.L >= 512) a.tb /= 2;
         a.ntiles = (g.M + a.tb - 1) / a.tb;
     }
-    const bool split = mode == ZM_GRAD && (!fixed_z || c.eng_z == ENG_F20 || a.tb * c.pz.L >= 512);
+    const bool split = mode == ZM_GRAD && (!fixed_z || eng_wide(eng) || a.tb * a.pf.L >= 512);
     // one block per tile and output, in XCD-aware order (xcd_order): the
     // gradient's blocks (one, or three when split) in a 1D grid, the other
     // modes' outputs along blockIdx.y
@@ -109,7 +118,7 @@ hipError_t launch_zfused(hipStream_t s, const GridDev &g, const LaunchCfg &c, co
     dim3 grid;
     if (mode == ZM_GRAD) grid = dim3(xcd_grid(nblk, G, split ? 3 : 1), 1);
     else grid = dim3(xcd_grid(nblk, G, 1), z_outputs(mode));
-    dim3 block(a.tb * c.pz.L);
+    dim3 block(a.tb * a.pf.L);
     size_t lds = zcol_lds_bytes(g.nz, a.tb);
 #define KW_ZMODES(ENGT, MAXT)                                                                  \
     do {                                                                                       \
@@ -123,12 +132,12 @@ hipError_t launch_zfused(hipStream_t s, const GridDev &g, const LaunchCfg &c, co
     } while (0)
     if (block.x > 512) {
         // wide tiles: 1024-thread instantiations of the fixed engines
-        if (c.eng_z == ENG_F16) KW_ZMODES(EngFixed<16>, 1024);
-        else if (c.eng_z == ENG_F8) KW_ZMODES(EngFixed<8>, 1024);
+        if (eng == ENG_F16) KW_ZMODES(EngFixed<16>, 1024);
+        else if (eng == ENG_F8) KW_ZMODES(EngFixed<8>, 1024);
         else return hipErrorInvalidConfiguration;
         return hipGetLastError();
     }
-    KW_ENGINE_SWITCH(c.eng_z, KW_ZMODES(Eng, 512));
+    KW_ENGINE_SWITCH(eng, KW_ZMODES(Eng, 512));
 #undef KW_ZMODES
     return hipGetLastError();
 }

@@ -136,10 +136,14 @@ struct StepBuffers {
 // FFT engines: generic one-butterfly-per-thread Stockham with register arrays
 // of 16 or 32 (any 2^a 3^b 5^c length), or the fixed-width engine with 8 or 16
 // elements per thread (power-of-two lengths, radices 2/4/8/16).
-enum EngId { ENG_G16 = 0, ENG_G32 = 1, ENG_F8 = 2, ENG_F16 = 3, ENG_F4 = 4, ENG_F12 = 5, ENG_F20 = 6 };
+enum EngId { ENG_G16 = 0, ENG_G32 = 1, ENG_F8 = 2, ENG_F16 = 3, ENG_F4 = 4, ENG_F12 = 5, ENG_F20 = 6,
+             ENG_F32 = 7 };
 inline bool eng_fixed(int e) {
-    return e == ENG_F4 || e == ENG_F8 || e == ENG_F16 || e == ENG_F12 || e == ENG_F20;
+    return e == ENG_F4 || e == ENG_F8 || e == ENG_F16 || e == ENG_F12 || e == ENG_F20 || e == ENG_F32;
 }
+// fixed engines whose register arrays are too wide for the kernels that keep
+// a second spectrum or sums per thread (they take the generic engines' paths)
+inline bool eng_wide(int e) { return e == ENG_F20 || e == ENG_F32; }
 
 struct LaunchCfg {
     int eng_x, eng_y, eng_z; // EngId per axis
@@ -150,6 +154,9 @@ struct LaunchCfg {
     int tb_den;              // rows per block of the three-group density kernel (generic engines)
     int tb_y;                // columns per block in y kernels
     int tb_z;                // columns per block in z kernels
+    int eng_za;              // the merged absorption z pass: engine, plans and
+    FftPlan pza, pzai;       // columns per block (the z pass's own unless a
+    int tb_za;               // better one is known for its length)
 };
 
 // LDS of the three-group density kernel (generic engines): the FFT buffers
