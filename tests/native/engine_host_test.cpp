@@ -253,6 +253,44 @@ int run_errors() {
         rc = kw_create_static(&in.grid, &in.medium, &in.source, &in.sensor, w3.p, w3.n, nullptr, &st);
         EXPECT(rc == KW_EUNSUPPORTED && !st, "static create of a grid too large returned %d", rc);
     }
+    // reverse mode with step records: argument checks, the step a record
+    // advances, and failed launches reported as such
+    {
+        kw_sim *sm = nullptr;
+        Buffer w4(need);
+        EXPECT(kw_create(&in.grid, &in.medium, &in.source, &in.sensor, w4.p, w4.n, nullptr, &sm) == KW_OK,
+               "create for the adjoint: %s", kw_last_error());
+        const int T = 4;
+        const size_t anb = kw_adjoint_workspace_size(sm, T);
+        EXPECT(anb > 0, "adjoint workspace size");
+        Buffer aw(anb);
+        std::vector<float> weights(in.npts, 1.0f);
+        kw_adj *adj = nullptr;
+        EXPECT(kw_adjoint_create(sm, weights.data(), T, aw.p, aw.n, &adj) == KW_OK && adj,
+               "adjoint create: %s", kw_last_error());
+        const int64_t rb = kw_adjoint_record_bytes(adj);
+        EXPECT(rb >= (int64_t)(7 * in.npts * sizeof(float)) && kw_adjoint_record_bytes(nullptr) == -1,
+               "record bytes %lld", (long long)rb);
+        Buffer rec((size_t)rb);
+        EXPECT(kw_adjoint_record(adj, nullptr, rec.n) == KW_EINVAL, "record into NULL");
+        EXPECT(kw_adjoint_record(adj, rec.p, rec.n - 1) == KW_EINVAL, "record one byte short");
+        kw_stats_t st0, st1;
+        EXPECT(kw_stats(sm, &st0) == KW_OK, "stats");
+        EXPECT(kw_adjoint_record(adj, rec.p, rec.n) == KW_OK, "record: %s", kw_last_error());
+        EXPECT(kw_stats(sm, &st1) == KW_OK && st1.steps == st0.steps + 1, "a record advances one step");
+        EXPECT(kw_adjoint_step_record(adj, T, rec.p, rec.n) == KW_EINVAL, "reverse step out of range");
+        EXPECT(kw_adjoint_step_record(adj, 0, rec.p, rec.n - 1) == KW_EINVAL, "reverse step, short record");
+        EXPECT(kw_adjoint_step_record(adj, 0, nullptr, rec.n) == KW_EINVAL, "reverse step, NULL record");
+        EXPECT(kw_adjoint_step_record(adj, 0, rec.p, rec.n) == KW_OK, "reverse step: %s", kw_last_error());
+        kw_stub_fail_launches = 1;
+        rc = kw_adjoint_record(adj, rec.p, rec.n);
+        EXPECT(rc == KW_EDEVICE, "record with failing launches returned %d", rc);
+        rc = kw_adjoint_step_record(adj, 0, rec.p, rec.n);
+        EXPECT(rc == KW_EDEVICE, "reverse step with failing launches returned %d", rc);
+        kw_stub_fail_launches = 0;
+        EXPECT(kw_step(sm, 1) == KW_OK, "step after a failed record");
+        EXPECT(kw_adjoint_destroy(adj) == KW_OK && kw_destroy(sm) == KW_OK, "adjoint destroy");
+    }
     std::printf("error paths ok\n");
     return 0;
 }
