@@ -9,6 +9,10 @@ calibrates the HBM traffic counters.
     python -m paper_1408_4675_amd.profiling copy [--mib N] [--reps K]
         a device-to-device copy of N MiB, K times (the reference kernel whose
         FETCH_SIZE / WRITE_SIZE give bytes-per-KiB scale factors)
+    python -m paper_1408_4675_amd.profiling zcopy --out FILE.md
+        build and run probes/zcol_copy.hip, a copy with the z passes' HBM
+        access pattern (column tiles of packed spectra, no transform), and
+        write its table: the bandwidth ceiling of a z pass for a tile width
     python -m paper_1408_4675_amd.profiling stats DIR --out FILE.md --title T --command C [--min-us U]
         turn the kernel_stats.csv that `rocprofv3 --kernel-trace --stats
         --output-format csv` wrote under DIR into a short Markdown table (with
@@ -210,6 +214,29 @@ def copy_probe(mib: int, reps: int):
     print("copied %d MiB %d times" % (mib, reps), flush=True)
 
 
+def zcopy_probe(out: str, command: str):
+    import shutil
+    import subprocess
+    import tempfile
+    from . import build as B
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "probes", "zcol_copy.hip")
+    with tempfile.TemporaryDirectory(prefix="kwprobe_") as tmp:
+        exe = os.path.join(tmp, "zcol_copy")
+        subprocess.run([B._hipcc(), "--offload-arch=" + B.ARCH, "-O3"] + B.DEVICE_FLAGS
+                       + [src, "-o", exe], check=True)
+        r = subprocess.run([exe], stdout=subprocess.PIPE, text=True, check=True)
+    print(r.stdout, flush=True)
+    with open(out, "w") as fh:
+        fh.write("# Column-tile copy: the HBM ceiling of the z passes' access pattern\n\n")
+        fh.write("Command (from the repository root, on one MI355X):\n\n    %s\n\n" % command)
+        fh.write("A block copies a tile of adjacent columns of a field of packed spectra\n"
+                 "(loads first, then stores; 'exchange' adds one LDS round trip with\n"
+                 "barriers); bytes per row is the contiguous run a tile reads and writes\n"
+                 "in each z plane.  TB/s counts the bytes read and written.\n\n")
+        fh.write(r.stdout)
+    print("wrote", out)
+
+
 def run_workload(name: str, steps: int, warmup: int, eager: bool):
     import time
     import torch
@@ -260,6 +287,8 @@ def main(argv=None):
     p = sub.add_parser("copy")
     p.add_argument("--mib", type=int, default=1024)
     p.add_argument("--reps", type=int, default=5)
+    p = sub.add_parser("zcopy")
+    p.add_argument("--out", required=True)
     p = sub.add_parser("stats")
     p.add_argument("dir")
     p.add_argument("--out", required=True)
@@ -278,6 +307,8 @@ def main(argv=None):
         run_workload(a.workload, a.steps, a.warmup, a.eager)
     elif a.cmd == "copy":
         copy_probe(a.mib, a.reps)
+    elif a.cmd == "zcopy":
+        zcopy_probe(a.out, "python -m paper_1408_4675_amd.profiling zcopy --out " + a.out)
     elif a.cmd == "stats":
         with open(a.out, "w") as fh:
             fh.write(stats_markdown(a.dir, a.title, a.command, a.min_us))

@@ -80,10 +80,20 @@ def test_bench_traffic_only_for_the_profiled_grid():
     current = d.get("source_hash") == P.kernel_source_hash()
     npts = d.get("points")
     assert npts == 256 ** 3
-    # another grid never gets the table's bytes
-    assert bench.measured_traffic("xden", 1024 ** 3) is None
+    # a grid without a table of its own never gets another grid's bytes
+    assert bench.measured_traffic("xden", 512 ** 3) is None
     got = bench.measured_traffic("xden", npts)
     if current:
         assert got == pytest.approx(d["kernels"]["xden"]["hbm_bytes_per_launch"])
     else:
         assert got is None
+    # the 1024^3 table serves the 1024^3 grid only, with its own figures
+    with open(os.path.join(ROOT, "profiles", "pmc_traffic_water_bowl_1024.json")) as fh:
+        d2 = json.load(fh)
+    assert d2.get("points") == 1024 ** 3
+    got2 = bench.measured_traffic("xden", 1024 ** 3)
+    if d2.get("source_hash") == P.kernel_source_hash():
+        assert got2 == pytest.approx(d2["kernels"]["xden"]["hbm_bytes_per_launch"])
+        assert got2 != pytest.approx(d["kernels"]["xden"]["hbm_bytes_per_launch"])
+    else:
+        assert got2 is None
