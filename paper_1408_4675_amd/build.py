@@ -37,6 +37,7 @@ def _run(cmd):
 
 HIP_SOURCES = ("kernels_yz.hip", "kernels_x.hip", "kernels_util.hip", "kernels_adj.hip",
                "static_scratch.hip")
+PROBE_SOURCES = ("zcol_copy.hip",)
 
 
 def build(verbose: bool = False, extra_flags=()) -> str:
@@ -51,6 +52,13 @@ def build(verbose: bool = False, extra_flags=()) -> str:
             objs.append(obj)
             cmd = ([hipcc, "-x", "hip", "--offload-arch=" + ARCH] + COMMON + DEVICE_FLAGS
                    + list(extra_flags) + ["-c", os.path.join(CSRC, src), "-o", obj])
+            jobs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE,
+                                               stderr=subprocess.STDOUT, text=True)))
+        # the measurement probes are programs of their own (built and run by
+        # profiling.py); compiled here too so that a build checks them
+        for src in PROBE_SOURCES:
+            cmd = ([hipcc, "-x", "hip", "--offload-arch=" + ARCH, "-O3", "-std=c++17"] + DEVICE_FLAGS
+                   + ["-c", os.path.join(HERE, "probes", src), "-o", os.path.join(tmp, src + ".o")])
             jobs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE,
                                                stderr=subprocess.STDOUT, text=True)))
         e_obj = os.path.join(tmp, "engine.o")
