@@ -269,8 +269,11 @@ int kw_set_graph(kw_sim *sim, int32_t steps_per_graph);
  * (0 = the default).  radices lists the factors of the transform length in
  * forward order (product must equal the length: nx/2 for x).  For a
  * power-of-two length, radices of at most 4, 8 or 16 (each a power of two)
- * run on the 4-, 8- or 16-wide fixed engine; other schedules on the generic
- * one.  Used by the autotuner; must be called before the first kw_step.
+ * run on the 4-, 8- or 16-wide fixed engine, and a schedule of radix-32
+ * passes only on the 32-wide one; for a length with a factor 3 or 5, radices
+ * that all divide 12 or 20 on the 12- or 20-wide fixed engine; other
+ * schedules on the generic one.  Used by the autotuner; must be called
+ * before the first kw_step.
  * Returns KW_EINVAL for radices that do not form a schedule of the length,
  * KW_EUNSUPPORTED for a tile that does not fit a block (the plan is then
  * left as it was), KW_ESTATE after the first step. */

@@ -105,8 +105,9 @@ def candidates(axis: int, n: int) -> List[Tuple[List[int], int]]:
         # keep the shortest schedules (at most one pass more than the minimum)
         mn = min(len(s) for s in scheds)
         scheds = [s for s in scheds if len(s) <= mn + 1]
-        if n >= 64:
-            scheds += [s for s in _factorisations(n, (32, 16, 8), 2) if 32 in s]
+        if n >= 32:
+            # the 32-wide fixed engine: radix-32 passes only
+            scheds += _factorisations(n, (32,), 3)
         # the four-wide fixed engine (radices up to 4: more passes, fewer
         # registers per thread)
         four = _factorisations(n, (4, 2), 8)

@@ -151,7 +151,8 @@ bool fixed_plan_from_radices(int n, int E, const std::vector<int> &rad, FftPlan 
     p.rmax = 0;
     for (int i = 0; i < p.np; ++i) {
         const int r = rad[i];
-        if (r < 2 || r > E || E % r) return false;
+        // (the 32-wide engine runs radix-32 passes only)
+        if (r < 2 || r > E || E % r || (E == 32 && r != 32)) return false;
         p.radix[i] = r;
         p.code |= (unsigned long long)r << (6 * i);
         prod *= r;
@@ -218,7 +219,9 @@ bool axis_plan(int n, int axis, const std::vector<int> *rad, int &eng, FftPlan &
         std::vector<int> r;
         if (rad) {
             r = *rad;
-            // the width is the largest radix of a caller-chosen schedule
+            // the width is the largest radix of a caller-chosen schedule (a
+            // schedule with radix 32 and smaller radices is not a fixed-engine
+            // plan: it runs on the generic engine)
             const int rm = *std::max_element(r.begin(), r.end());
             E = rm > 16 ? 32 : rm > 8 ? 16 : rm > 4 ? 8 : 4;
         } else {
@@ -232,6 +235,9 @@ bool axis_plan(int n, int axis, const std::vector<int> *rad, int &eng, FftPlan &
         }
         if (fixed_plan_from_radices(n, E, r, f)) {
             eng = E == 32 ? ENG_F32 : E == 16 ? ENG_F16 : E == 8 ? ENG_F8 : ENG_F4;
+            // a plan of radix-E passes only runs on the kernels built for it
+            if ((E == 8 || E == 16) && std::all_of(r.begin(), r.end(), [E](int q) { return q == E; }))
+                eng = E == 16 ? ENG_F16P : ENG_F8P;
             i = f;
             return true;
         }
@@ -787,15 +793,16 @@ int pick_tiles(kw_sim *s, int tile_y, int tile_z) {
         while (tb > 1 && (tb * L > max_threads || bytes(n, tb) > max_bytes)) tb /= 2;
         return tb;
     };
-    c.tb_y = col_tile(g.ny, c.py.L, tile_y, c.eng_y == ENG_F8 || c.eng_y == ENG_F16, col_lds_bytes,
+    const int gy = eng_general(c.eng_y), gz = eng_general(c.eng_z);
+    c.tb_y = col_tile(g.ny, c.py.L, tile_y, gy == ENG_F8 || gy == ENG_F16, col_lds_bytes,
                       c.eng_y == ENG_F32);
-    c.tb_z = col_tile(g.nz, c.pz.L, tile_z, c.eng_z == ENG_F8 || c.eng_z == ENG_F16, zcol_lds_bytes,
+    c.tb_z = col_tile(g.nz, c.pz.L, tile_z, gz == ENG_F8 || gz == ENG_F16, zcol_lds_bytes,
                       c.eng_z == ENG_F32);
     int rc;
     if ((rc = check_tb("x pass", c.tb_x, c.px.L, x_lds_bytes(g.M, g.nx, c.tb_x, true))) != KW_OK)
         return rc;
-    const bool wide_y = c.eng_y == ENG_F8 || c.eng_y == ENG_F16;
-    const bool wide_z = c.eng_z == ENG_F8 || c.eng_z == ENG_F16;
+    const bool wide_y = gy == ENG_F8 || gy == ENG_F16;
+    const bool wide_z = gz == ENG_F8 || gz == ENG_F16;
     if ((rc = check_tb("y pass", c.tb_y, c.py.L, col_lds_bytes(g.ny, c.tb_y), wide_y,
                        s->max_lds, c.eng_y == ENG_F32)) != KW_OK)
         return rc;
@@ -811,7 +818,7 @@ int pick_tiles(kw_sim *s, int tile_y, int tile_z) {
     c.pza = c.pz;
     c.pzai = c.pzi;
     c.tb_za = c.tb_z;
-    if (g.nz == 1024 && c.eng_z == ENG_F16) {
+    if (g.nz == 1024 && gz == ENG_F16) {
         FftPlan f;
         if (fixed_plan_from_radices(1024, 32, {32, 32}, f) && 16 * f.L <= 512 &&
             zcol_lds_bytes(g.nz, 16) <= s->max_lds) {

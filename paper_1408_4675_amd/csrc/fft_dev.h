@@ -344,7 +344,8 @@ __device__ __forceinline__ void fft_run(const FftPlan &P, const float2 *__restri
 // schedule (every radix divides E).  A pass of radix R runs E/R butterflies per
 // thread, j = t + b L (b < E/R); butterfly j reads x[j + r n/R], which is
 // element t + L (b + r E/R) -- register b + r E/R.
-// E = 4, 8, 16, 32 serve power-of-two lengths (radices 2 to 32); E = 12 and
+// E = 4, 8, 16 serve power-of-two lengths (radices 2 to 16) and E = 32 the
+// powers of 32 (radix-32 passes only); E = 12 and
 // E = 20 serve lengths with a factor 3 or 5 (radices 2, 3, 4, 6, 12 and
 // 2, 4, 5, 10, 20), where the butterfly's position k = j mod Ns within its
 // group is no longer a bit mask.
@@ -385,7 +386,8 @@ __device__ __forceinline__ void pass_fixed(float2 (&v)[E], int t, int L, int Ns,
 }
 
 // On entry v[m] = x[t + m L]; on exit v[m] = X[t + m L] (m < E, t < L).
-template <bool INV, int E, class Lds>
+// PURE: every pass of the plan has radix E (only that pass is compiled)
+template <bool INV, int E, bool PURE, class Lds>
 __device__ __forceinline__ void fft_fixed(const FftPlan &P, const float2 *__restrict__ tw, int t,
                                           const Lds &lds, float2 (&v)[E]) {
     const int L = P.L;
@@ -401,6 +403,16 @@ __device__ __forceinline__ void fft_fixed(const FftPlan &P, const float2 *__rest
         const int st = P.n / (Ns * R);
         const bool write = p < P.np - 1;
         // (a plan holds only radices that divide E)
+        if constexpr (PURE || E == 32) {
+            // Plans of one radix, and the 32-wide engine, which runs radix-32
+            // passes only: the code of the other radices (a switch on the
+            // pass's radix) raises the register count of every kernel built
+            // on the engine, though only one of them runs.  Measured without
+            // it: the 32-wide y pass 206 -> 124 registers and its merged
+            // absorption z pass 284 -> 60 bytes a thread spilled; the 16-wide
+            // y pass 106 -> 68, the 8-wide velocity x pass 114 -> 96.
+            pass_fixed<E, E, INV>(v, t, L, Ns, st, tw, lds, write);
+        } else
         switch (R) {
         case 2: pass_fixed<E, 2, INV>(v, t, L, Ns, st, tw, lds, write); break;
         case 4: if constexpr (E % 4 == 0) pass_fixed<E, 4, INV>(v, t, L, Ns, st, tw, lds, write); break;
@@ -455,7 +467,8 @@ struct EngGeneric {
     }
 };
 
-template <int EE>
+// PURE: the plans run on this instantiation have radix-E passes only
+template <int EE, bool PURE = false>
 struct EngFixed {
     static constexpr int E = EE;
     static constexpr bool fixed = true;
@@ -472,8 +485,10 @@ struct EngFixed {
     template <bool INV, class Lds>
     __device__ static __forceinline__ void run(const FftPlan &P, const float2 *tw, int t,
                                                const Lds &lds, float2 (&v)[EE]) {
-        fft_fixed<INV, EE>(P, tw, t, lds, v);
+        fft_fixed<INV, EE, PURE>(P, tw, t, lds, v);
     }
 };
+using EngFixed8P = EngFixed<8, true>;
+using EngFixed16P = EngFixed<16, true>;
 
 }  // namespace kw

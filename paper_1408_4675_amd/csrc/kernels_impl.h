@@ -1456,6 +1456,8 @@ __global__ void __launch_bounds__(512) kw_xinv(XArgs a) {
     case ENG_G32: { using Eng = EngGeneric<32>; BODY; } break;                 \
     case ENG_F4:  { using Eng = EngFixed<4>; BODY; } break;                    \
     case ENG_F8:  { using Eng = EngFixed<8>; BODY; } break;                    \
+    case ENG_F8P: { using Eng = EngFixed8P; BODY; } break;              \
+    case ENG_F16P: { using Eng = EngFixed16P; BODY; } break;            \
     case ENG_F12: { using Eng = EngFixed<12>; BODY; } break;                   \
     case ENG_F20: { using Eng = EngFixed<20>; BODY; } break;                   \
     case ENG_F32: { using Eng = EngFixed<32>; BODY; } break;                   \

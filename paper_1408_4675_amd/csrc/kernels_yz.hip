@@ -36,6 +36,12 @@ hipError_t launch_ypass(hipStream_t s, const GridDev &g, const LaunchCfg &c, con
         if (c.eng_y == ENG_F16) {
             if (inverse) hipLaunchKernelGGL((kw_ypass<EngFixed<16>, true, 1024>), grid, block, lds, s, a);
             else hipLaunchKernelGGL((kw_ypass<EngFixed<16>, false, 1024>), grid, block, lds, s, a);
+        } else if (c.eng_y == ENG_F16P) {
+            if (inverse) hipLaunchKernelGGL((kw_ypass<EngFixed16P, true, 1024>), grid, block, lds, s, a);
+            else hipLaunchKernelGGL((kw_ypass<EngFixed16P, false, 1024>), grid, block, lds, s, a);
+        } else if (c.eng_y == ENG_F8P) {
+            if (inverse) hipLaunchKernelGGL((kw_ypass<EngFixed8P, true, 1024>), grid, block, lds, s, a);
+            else hipLaunchKernelGGL((kw_ypass<EngFixed8P, false, 1024>), grid, block, lds, s, a);
         } else if (c.eng_y == ENG_F8) {
             if (inverse) hipLaunchKernelGGL((kw_ypass<EngFixed<8>, true, 1024>), grid, block, lds, s, a);
             else hipLaunchKernelGGL((kw_ypass<EngFixed<8>, false, 1024>), grid, block, lds, s, a);
@@ -133,6 +139,8 @@ hipError_t launch_zfused(hipStream_t s, const GridDev &g, const LaunchCfg &c, co
     if (block.x > 512) {
         // wide tiles: 1024-thread instantiations of the fixed engines
         if (eng == ENG_F16) KW_ZMODES(EngFixed<16>, 1024);
+        else if (eng == ENG_F16P) KW_ZMODES(EngFixed16P, 1024);
+        else if (eng == ENG_F8P) KW_ZMODES(EngFixed8P, 1024);
         else if (eng == ENG_F8) KW_ZMODES(EngFixed<8>, 1024);
         else return hipErrorInvalidConfiguration;
         return hipGetLastError();

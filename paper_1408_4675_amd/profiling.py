@@ -62,7 +62,9 @@ def kernel_source_hash() -> str:
 
 def kernel_class(name: str) -> Optional[str]:
     """Class of a demangled kernel name (None for kernels of other code)."""
-    m = re.search(r"kw_ypass<.*?, (true|false)(, \d+)?>", name)
+    # (the engine is the first template argument, itself a template: the
+    # direction flag is the first argument after it)
+    m = re.search(r"kw_ypass<(?:kw::)?Eng\w+<[^<>]*>, (true|false)(, \d+)?>", name)
     if m:
         return "ypass_inv" if m.group(1) == "true" else "ypass_fwd"
     m = re.search(r"kw_zfused<.*?>, (\d)(, \d+)?(, (true|false))?>", name)

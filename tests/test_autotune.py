@@ -29,6 +29,15 @@ def test_power_of_two_lengths_offer_every_fixed_width(n):
     assert {4, 8, 16} <= widths
 
 
+@pytest.mark.parametrize("n", [32, 64, 512, 1024])
+def test_radix32_candidates_are_fixed_engine_plans(n):
+    """Candidates with a radix-32 pass are radix-32 passes only (the schedules
+    the 32-wide fixed engine runs): 32 and 1024 have one, 64 and 512 none."""
+    s32 = [s for s, _ in T.candidates(1, n) if 32 in s]
+    assert all(set(s) == {32} for s in s32)
+    assert bool(s32) == (n in (32, 1024))
+
+
 def test_shipped_table_is_well_formed():
     with open(os.path.join(ROOT, "paper_1408_4675_amd", "tuning", "gfx950.json")) as fh:
         tab = json.load(fh)

@@ -374,11 +374,14 @@ def test_parity_constant_rho0_absorbing(kw, shape):
 # per thread, radices dividing 12 or 20, butterfly groups of non-power-of-two
 # size): x rows of 24, 40 and 48 points (density pass in three thread groups),
 # y and z columns of 24 to 100 points, next to generic-engine axes; and the
-# 32-wide fixed engine on x rows, y and z columns (1024 points in two passes).
+# 32-wide fixed engine (radix-32 passes only) on x rows, y and z columns
+# (1024 points in two passes), next to radix-32 schedules with a radix-2 pass,
+# which run on the generic engine.
 MIXED = [((48, 40, 36), [(0, [12, 2]), (1, [20, 2]), (2, [12, 3])]),
          # the 32-wide fixed engine (two radix-32 passes for 1024 points)
          ((16, 64, 1024), [(1, [32, 2]), (2, [32, 32])]),
          ((128, 32, 48), [(0, [32, 2]), (1, [32])]),
+         ((64, 32, 48), [(0, [32]), (1, [32])]),
          ((80, 24, 60), [(0, [20, 2]), (1, [12, 2])]),
          ((96, 36, 40), [(0, [12, 4]), (1, [6, 6]), (2, [10, 4])]),
          ((40, 48, 100), [(1, [4, 4, 3]), (2, [20, 5])])]

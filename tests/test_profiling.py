@@ -16,6 +16,10 @@ from paper_1408_4675_amd import profiling as P  # noqa: E402
 @pytest.mark.parametrize("name,cls", [
     ("void kw::kw_ypass<kw::EngFixed<8>, true, 512>(kw::YArgs)", "ypass_inv"),
     ("void kw::kw_ypass<kw::EngFixed<16>, false, 1024>(kw::YArgs)", "ypass_fwd"),
+    # single-radix engines carry a second template argument (true)
+    ("void kw::kw_ypass<kw::EngFixed<16, true>, false, 512>(kw::YArgs)", "ypass_fwd"),
+    ("void kw::kw_ypass<kw::EngFixed<8, true>, true, 1024>(kw::YArgs)", "ypass_inv"),
+    ("void kw::kw_zfused<kw::EngFixed<16, true>, 1, 512, false>(kw::ZArgs)", "zfused_div"),
     ("void kw::kw_zfused<kw::EngFixed<16>, 0, 512>(kw::ZArgs)", "zfused_grad"),
     ("void kw::kw_zfused<kw::EngGeneric<16>, 1, 512>(kw::ZArgs)", "zfused_div"),
     ("void kw::kw_zfused<kw::EngFixed<8>, 5, 1024>(kw::ZArgs)", "zfused_abs"),
