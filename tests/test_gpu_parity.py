@@ -321,6 +321,26 @@ def test_parity_long_axes(kw, shape):
         assert e <= tol, (k, e)
 
 
+# Plans whose passes all have one radix run on kernels built for that radix
+# alone (16·16 for 256 points and 8·8·8 for 512 by default): the 16-wide on
+# y columns and x rows, the 8-wide on y and z columns (z columns of 256 and x
+# rows of 512 points are in the long-axis cases above)
+SINGLE = [((16, 256, 8), []),
+          ((512, 6, 8), [(0, [16, 16])]),
+          ((16, 64, 512), [(1, [8, 8]), (2, [8, 8, 8])])]
+
+
+@pytest.mark.parametrize("shape,plans", SINGLE, ids=["%dx%dx%d" % c[0] for c in SINGLE])
+def test_parity_single_radix_engines(kw, shape, plans):
+    nx, ny, nz = shape
+    scen = sc.small_case(nx, ny, nz, seed=17, heterogeneous=True, nonlinear=True, absorbing=True,
+                         pml=2, steps=6, sensor_mask=True)
+    sim, orc = _run_both(kw, scen, 6, plans=plans)
+    errs, tol = compare_outputs(sim, orc, scen, REPORT)
+    for k, e in errs.items():
+        assert e <= tol, (k, e)
+
+
 # Homogeneous absorbing water (scalar c0^2 tau, c0^2 eta): the merged
 # absorption z pass (one inverse transform for both terms of Eq. (8)), which
 # the 1024^3 water workload runs at 1024 points in half-width tiles, and the
