@@ -210,6 +210,9 @@ bool axis_plan(int n, int axis, const std::vector<int> *rad, int &eng, FftPlan &
         }
         if (E && fixed_plan_from_radices(n, E, r, f)) {
             eng = E == 12 ? ENG_F12 : ENG_F20;
+            // a plan of radices 6 and 4 runs on the kernels built for them
+            if (E == 12 && std::all_of(r.begin(), r.end(), [](int q) { return q == 6 || q == 4; }))
+                eng = ENG_F12_64;
             i = f;
             return true;
         }
@@ -768,7 +771,7 @@ int pick_tiles(kw_sim *s, int tile_y, int tile_z) {
     while (c.tb_x > 1 && x_lds_bytes(g.M, g.nx, c.tb_x, true) > 64 * 1024) c.tb_x /= 2;
     // rows per block of the three-group density kernel of the generic
     // engines: as many as fit 512 threads and 64 KB of LDS
-    if (!eng_fixed(c.eng_x) || c.eng_x == ENG_F12 || eng_wide(c.eng_x)) {
+    if (!eng_fixed(c.eng_x) || eng_general(c.eng_x) == ENG_F12 || eng_wide(c.eng_x)) {
         const bool line = den_needs_line(s->med, s->src, s->sen);
         auto fits = [&](int tb) {
             return 3 * tb * c.px.L <= 512 && den_lds_bytes(g.M, g.nx, tb, line) <= 64 * 1024;

@@ -386,8 +386,27 @@ __device__ __forceinline__ void pass_fixed(float2 (&v)[E], int t, int L, int Ns,
 }
 
 // On entry v[m] = x[t + m L]; on exit v[m] = X[t + m L] (m < E, t < L).
-// PURE: every pass of the plan has radix E (only that pass is compiled)
-template <bool INV, int E, bool PURE, class Lds>
+// A set of radices: bit q stands for radix q (0: every radix that divides E)
+using RadixSet = unsigned long long;
+constexpr RadixSet radix_bit(int q) { return 1ull << q; }
+
+// One pass of radix R, where R is known to be in the set RS: only the passes
+// of RS are compiled (the largest radix first)
+template <int E, RadixSet RS, bool INV, class Lds>
+__device__ __forceinline__ void pass_in_set(int R, float2 (&v)[E], int t, int L, int Ns, int st,
+                                            const float2 *__restrict__ tw, const Lds &lds,
+                                            bool write) {
+    constexpr int q = 63 - __builtin_clzll(RS);
+    if constexpr ((RS & (RS - 1)) == 0) {
+        pass_fixed<E, q, INV>(v, t, L, Ns, st, tw, lds, write);
+    } else {
+        if (R == q) pass_fixed<E, q, INV>(v, t, L, Ns, st, tw, lds, write);
+        else pass_in_set<E, RS & ~radix_bit(q), INV>(R, v, t, L, Ns, st, tw, lds, write);
+    }
+}
+
+// RS: the radices of the plans this instantiation runs (0: any that divide E)
+template <bool INV, int E, RadixSet RS, class Lds>
 __device__ __forceinline__ void fft_fixed(const FftPlan &P, const float2 *__restrict__ tw, int t,
                                           const Lds &lds, float2 (&v)[E]) {
     const int L = P.L;
@@ -403,15 +422,16 @@ __device__ __forceinline__ void fft_fixed(const FftPlan &P, const float2 *__rest
         const int st = P.n / (Ns * R);
         const bool write = p < P.np - 1;
         // (a plan holds only radices that divide E)
-        if constexpr (PURE || E == 32) {
-            // Plans of one radix, and the 32-wide engine, which runs radix-32
-            // passes only: the code of the other radices (a switch on the
-            // pass's radix) raises the register count of every kernel built
-            // on the engine, though only one of them runs.  Measured without
-            // it: the 32-wide y pass 206 -> 124 registers and its merged
-            // absorption z pass 284 -> 60 bytes a thread spilled; the 16-wide
-            // y pass 106 -> 68, the 8-wide velocity x pass 114 -> 96.
-            pass_fixed<E, E, INV>(v, t, L, Ns, st, tw, lds, write);
+        if constexpr (RS != 0 || E == 32) {
+            // Instantiations for a set of radices, and the 32-wide engine,
+            // which runs radix-32 passes only: the code of the radices a plan
+            // does not use (a switch on the pass's radix) raises the register
+            // count of every kernel built on the engine, though it never runs.
+            // Measured without it: the 32-wide y pass 206 -> 124 registers and
+            // its merged absorption z pass 284 -> 60 bytes a thread spilled;
+            // the 16-wide y pass 106 -> 68, the 8-wide velocity x pass
+            // 114 -> 96, the 12-wide three-group density pass 98 -> 89.
+            pass_in_set<E, (RS != 0 ? RS : radix_bit(32)), INV>(R, v, t, L, Ns, st, tw, lds, write);
         } else
         switch (R) {
         case 2: pass_fixed<E, 2, INV>(v, t, L, Ns, st, tw, lds, write); break;
@@ -467,8 +487,9 @@ struct EngGeneric {
     }
 };
 
-// PURE: the plans run on this instantiation have radix-E passes only
-template <int EE, bool PURE = false>
+// RS: the radices of the plans run on this instantiation (0: any that
+// divide EE)
+template <int EE, RadixSet RS = 0>
 struct EngFixed {
     static constexpr int E = EE;
     static constexpr bool fixed = true;
@@ -485,10 +506,12 @@ struct EngFixed {
     template <bool INV, class Lds>
     __device__ static __forceinline__ void run(const FftPlan &P, const float2 *tw, int t,
                                                const Lds &lds, float2 (&v)[EE]) {
-        fft_fixed<INV, EE, PURE>(P, tw, t, lds, v);
+        fft_fixed<INV, EE, RS>(P, tw, t, lds, v);
     }
 };
-using EngFixed8P = EngFixed<8, true>;
-using EngFixed16P = EngFixed<16, true>;
+// plans of radix-8 (radix-16) passes only; plans of radices 6 and 4 at width 12
+using EngFixed8P = EngFixed<8, radix_bit(8)>;
+using EngFixed16P = EngFixed<16, radix_bit(16)>;
+using EngFixed12_64 = EngFixed<12, radix_bit(6) | radix_bit(4)>;
 
 }  // namespace kw

@@ -1459,6 +1459,7 @@ __global__ void __launch_bounds__(512) kw_xinv(XArgs a) {
     case ENG_F8P: { using Eng = EngFixed8P; BODY; } break;              \
     case ENG_F16P: { using Eng = EngFixed16P; BODY; } break;            \
     case ENG_F12: { using Eng = EngFixed<12>; BODY; } break;                   \
+    case ENG_F12_64: { using Eng = EngFixed12_64; BODY; } break;               \
     case ENG_F20: { using Eng = EngFixed<20>; BODY; } break;                   \
     case ENG_F32: { using Eng = EngFixed<32>; BODY; } break;                   \
     default:      { using Eng = EngFixed<16>; BODY; } break;                   \

@@ -75,7 +75,7 @@ hipError_t launch_xden(hipStream_t s, const GridDev &g, const LaunchCfg &c, cons
     a.Sout[0] = Sout[0];
     a.Sout[1] = Sout[1];
     a.rho_total = rho_total;
-    if (!eng_fixed(c.eng_x) || c.eng_x == ENG_F12 || eng_wide(c.eng_x)) {
+    if (!eng_fixed(c.eng_x) || eng_general(c.eng_x) == ENG_F12 || eng_wide(c.eng_x)) {
         // generic and mixed-radix engines: three thread groups per row (see
         // kw_xden3; their wider register arrays leave no room for the sums)
         a.tb = c.tb_den;
@@ -89,6 +89,7 @@ hipError_t launch_xden(hipStream_t s, const GridDev &g, const LaunchCfg &c, cons
     } while (0)
         if (c.eng_x == ENG_G16) KW_DEN3(EngGeneric<16>);
         else if (c.eng_x == ENG_F12) KW_DEN3(EngFixed<12>);
+        else if (c.eng_x == ENG_F12_64) KW_DEN3(EngFixed12_64);
         else if (c.eng_x == ENG_F20) KW_DEN3(EngFixed<20>);
         else if (c.eng_x == ENG_F32) KW_DEN3(EngFixed<32>);
         else KW_DEN3(EngGeneric<32>);

@@ -16,10 +16,12 @@ from paper_1408_4675_amd import profiling as P  # noqa: E402
 @pytest.mark.parametrize("name,cls", [
     ("void kw::kw_ypass<kw::EngFixed<8>, true, 512>(kw::YArgs)", "ypass_inv"),
     ("void kw::kw_ypass<kw::EngFixed<16>, false, 1024>(kw::YArgs)", "ypass_fwd"),
-    # single-radix engines carry a second template argument (true)
-    ("void kw::kw_ypass<kw::EngFixed<16, true>, false, 512>(kw::YArgs)", "ypass_fwd"),
-    ("void kw::kw_ypass<kw::EngFixed<8, true>, true, 1024>(kw::YArgs)", "ypass_inv"),
-    ("void kw::kw_zfused<kw::EngFixed<16, true>, 1, 512, false>(kw::ZArgs)", "zfused_div"),
+    # the fixed engine's second template argument is its set of radices
+    ("void kw::kw_ypass<kw::EngFixed<16, 65536ull>, false, 512>(kw::YArgs)", "ypass_fwd"),
+    ("void kw::kw_ypass<kw::EngFixed<8, 256ull>, true, 1024>(kw::YArgs)", "ypass_inv"),
+    ("void kw::kw_ypass<kw::EngFixed<16, 0ull>, true, 512>(kw::YArgs)", "ypass_inv"),
+    ("void kw::kw_zfused<kw::EngFixed<16, 65536ull>, 1, 512, false>(kw::ZArgs)", "zfused_div"),
+    ("void kw::kw_xden3<kw::EngFixed<12, 80ull>, true>(kw::XArgs)", "xden"),
     ("void kw::kw_zfused<kw::EngFixed<16>, 0, 512>(kw::ZArgs)", "zfused_grad"),
     ("void kw::kw_zfused<kw::EngGeneric<16>, 1, 512>(kw::ZArgs)", "zfused_div"),
     ("void kw::kw_zfused<kw::EngFixed<8>, 5, 1024>(kw::ZArgs)", "zfused_abs"),
