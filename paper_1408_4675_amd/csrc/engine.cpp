@@ -238,9 +238,12 @@ bool axis_plan(int n, int axis, const std::vector<int> *rad, int &eng, FftPlan &
         }
         if (fixed_plan_from_radices(n, E, r, f)) {
             eng = E == 32 ? ENG_F32 : E == 16 ? ENG_F16 : E == 8 ? ENG_F8 : ENG_F4;
-            // a plan of radix-E passes only runs on the kernels built for it
+            // plans of radix-E passes only, and 8-wide plans of radices 8
+            // and 4, run on the kernels built for those radices
             if ((E == 8 || E == 16) && std::all_of(r.begin(), r.end(), [E](int q) { return q == E; }))
                 eng = E == 16 ? ENG_F16P : ENG_F8P;
+            else if (E == 8 && std::all_of(r.begin(), r.end(), [](int q) { return q == 8 || q == 4; }))
+                eng = ENG_F8_84;
             i = f;
             return true;
         }

@@ -509,9 +509,11 @@ struct EngFixed {
         fft_fixed<INV, EE, RS>(P, tw, t, lds, v);
     }
 };
-// plans of radix-8 (radix-16) passes only; plans of radices 6 and 4 at width 12
+// plans of radix-8 (radix-16) passes only; plans of radices 8 and 4 at width
+// 8; plans of radices 6 and 4 at width 12
 using EngFixed8P = EngFixed<8, radix_bit(8)>;
 using EngFixed16P = EngFixed<16, radix_bit(16)>;
+using EngFixed8_84 = EngFixed<8, radix_bit(8) | radix_bit(4)>;
 using EngFixed12_64 = EngFixed<12, radix_bit(6) | radix_bit(4)>;
 
 }  // namespace kw

@@ -1457,6 +1457,7 @@ __global__ void __launch_bounds__(512) kw_xinv(XArgs a) {
     case ENG_F4:  { using Eng = EngFixed<4>; BODY; } break;                    \
     case ENG_F8:  { using Eng = EngFixed<8>; BODY; } break;                    \
     case ENG_F8P: { using Eng = EngFixed8P; BODY; } break;              \
+    case ENG_F8_84: { using Eng = EngFixed8_84; BODY; } break;          \
     case ENG_F16P: { using Eng = EngFixed16P; BODY; } break;            \
     case ENG_F12: { using Eng = EngFixed<12>; BODY; } break;                   \
     case ENG_F12_64: { using Eng = EngFixed12_64; BODY; } break;               \

@@ -115,6 +115,7 @@ hipError_t launch_xden(hipStream_t s, const GridDev &g, const LaunchCfg &c, cons
     if (c.eng_x == ENG_F4) KW_DEN1(EngFixed<4>);
     else if (c.eng_x == ENG_F8) KW_DEN1(EngFixed<8>);
     else if (c.eng_x == ENG_F8P) KW_DEN1(EngFixed8P);
+    else if (c.eng_x == ENG_F8_84) KW_DEN1(EngFixed8_84);
     else if (c.eng_x == ENG_F16P) KW_DEN1(EngFixed16P);
     else KW_DEN1(EngFixed<16>);
 #undef KW_DEN1

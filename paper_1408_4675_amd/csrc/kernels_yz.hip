@@ -42,6 +42,9 @@ hipError_t launch_ypass(hipStream_t s, const GridDev &g, const LaunchCfg &c, con
         } else if (c.eng_y == ENG_F8P) {
             if (inverse) hipLaunchKernelGGL((kw_ypass<EngFixed8P, true, 1024>), grid, block, lds, s, a);
             else hipLaunchKernelGGL((kw_ypass<EngFixed8P, false, 1024>), grid, block, lds, s, a);
+        } else if (c.eng_y == ENG_F8_84) {
+            if (inverse) hipLaunchKernelGGL((kw_ypass<EngFixed8_84, true, 1024>), grid, block, lds, s, a);
+            else hipLaunchKernelGGL((kw_ypass<EngFixed8_84, false, 1024>), grid, block, lds, s, a);
         } else if (c.eng_y == ENG_F8) {
             if (inverse) hipLaunchKernelGGL((kw_ypass<EngFixed<8>, true, 1024>), grid, block, lds, s, a);
             else hipLaunchKernelGGL((kw_ypass<EngFixed<8>, false, 1024>), grid, block, lds, s, a);
@@ -141,6 +144,7 @@ hipError_t launch_zfused(hipStream_t s, const GridDev &g, const LaunchCfg &c, co
         if (eng == ENG_F16) KW_ZMODES(EngFixed<16>, 1024);
         else if (eng == ENG_F16P) KW_ZMODES(EngFixed16P, 1024);
         else if (eng == ENG_F8P) KW_ZMODES(EngFixed8P, 1024);
+        else if (eng == ENG_F8_84) KW_ZMODES(EngFixed8_84, 1024);
         else if (eng == ENG_F8) KW_ZMODES(EngFixed<8>, 1024);
         else return hipErrorInvalidConfiguration;
         return hipGetLastError();

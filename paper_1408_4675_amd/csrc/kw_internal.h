@@ -137,13 +137,15 @@ struct StepBuffers {
 // of 16 or 32 (any 2^a 3^b 5^c length), or the fixed-width engine with 8 or 16
 // elements per thread (power-of-two lengths, radices 2/4/8/16).
 // ENG_F8P, ENG_F16P: the 8- and 16-wide fixed engines for plans whose passes
-// all have radix 8 (16); ENG_F12_64: the 12-wide one for plans of radices 6
-// and 4.  The kernels built for a set of radices hold fewer registers.
+// all have radix 8 (16); ENG_F8_84: the 8-wide one for plans of radices 8
+// and 4; ENG_F12_64: the 12-wide one for plans of radices 6 and 4.  The
+// kernels built for a set of radices hold fewer registers.
 enum EngId { ENG_G16 = 0, ENG_G32 = 1, ENG_F8 = 2, ENG_F16 = 3, ENG_F4 = 4, ENG_F12 = 5, ENG_F20 = 6,
-             ENG_F32 = 7, ENG_F8P = 8, ENG_F16P = 9, ENG_F12_64 = 10 };
+             ENG_F32 = 7, ENG_F8P = 8, ENG_F16P = 9, ENG_F12_64 = 10, ENG_F8_84 = 11 };
 // the engine of the same width that runs any plan (ENG_F8P -> ENG_F8, ...)
 inline int eng_general(int e) {
-    return e == ENG_F8P ? ENG_F8 : e == ENG_F16P ? ENG_F16 : e == ENG_F12_64 ? ENG_F12 : e;
+    return (e == ENG_F8P || e == ENG_F8_84) ? ENG_F8 : e == ENG_F16P ? ENG_F16
+         : e == ENG_F12_64 ? ENG_F12 : e;
 }
 inline bool eng_fixed(int e) {
     e = eng_general(e);

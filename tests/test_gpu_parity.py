@@ -324,11 +324,14 @@ def test_parity_long_axes(kw, shape):
 # Plans whose passes all have one radix run on kernels built for that radix
 # alone (16·16 for 256 points and 8·8·8 for 512 by default): the 16-wide on
 # y columns and x rows, the 8-wide on y and z columns (z columns of 256 and x
-# rows of 512 points are in the long-axis cases above); plans of radices 6
-# and 4 on the 12-wide kernels built for those two
+# rows of 512 points are in the long-axis cases above); plans of radices 8
+# and 4 (6 and 4) on the 8-wide (12-wide) kernels built for those two
 SINGLE = [((16, 256, 8), []),
           ((512, 6, 8), [(0, [16, 16])]),
           ((16, 64, 512), [(1, [8, 8]), (2, [8, 8, 8])]),
+          # radices 8 and 4 at width 8 (the 256^3 rows' schedule 8·4·4)
+          ((256, 8, 6), [(0, [8, 4, 4])]),
+          ((8, 128, 32), [(1, [8, 4, 4]), (2, [8, 4])]),
           # radices 6 and 4 at width 12 (the 192^3 rows' schedule)
           ((192, 12, 10), [(0, [6, 4, 4])]),
           ((40, 96, 24), [(1, [6, 4, 4]), (2, [6, 4])])]
