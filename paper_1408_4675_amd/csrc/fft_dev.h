@@ -385,7 +385,6 @@ __device__ __forceinline__ void pass_fixed(float2 (&v)[E], int t, int L, int Ns,
     FixedBfly<E, R, INV, 0>::run(v, t, L, Ns, st, tw, lds, write);
 }
 
-// On entry v[m] = x[t + m L]; on exit v[m] = X[t + m L] (m < E, t < L).
 // A set of radices: bit q stands for radix q (0: every radix that divides E)
 using RadixSet = unsigned long long;
 constexpr RadixSet radix_bit(int q) { return 1ull << q; }
@@ -405,6 +404,7 @@ __device__ __forceinline__ void pass_in_set(int R, float2 (&v)[E], int t, int L,
     }
 }
 
+// On entry v[m] = x[t + m L]; on exit v[m] = X[t + m L] (m < E, t < L).
 // RS: the radices of the plans this instantiation runs (0: any that divide E)
 template <bool INV, int E, RadixSet RS, class Lds>
 __device__ __forceinline__ void fft_fixed(const FftPlan &P, const float2 *__restrict__ tw, int t,
