@@ -332,6 +332,10 @@ SINGLE = [((16, 256, 8), []),
           # radices 8 and 4 at width 8 (the 256^3 rows' schedule 8·4·4)
           ((256, 8, 6), [(0, [8, 4, 4])]),
           ((8, 128, 32), [(1, [8, 4, 4]), (2, [8, 4])]),
+          # the 1024-thread blocks of these kernels (16 columns of 64 and of
+          # 128 threads)
+          ((16, 512, 8), [(1, [8, 8, 8])]),
+          ((16, 8, 1024), [(2, [8, 8, 4, 4])]),
           # radices 6 and 4 at width 12 (the 192^3 rows' schedule)
           ((192, 12, 10), [(0, [6, 4, 4])]),
           ((40, 96, 24), [(1, [6, 4, 4]), (2, [6, 4])])]
