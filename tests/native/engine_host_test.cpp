@@ -295,12 +295,60 @@ int run_errors() {
     return 0;
 }
 
+// kw_set_plan: schedules for each kind of FFT engine instantiation are
+// accepted (fixed widths 8, 16 and 32, the radix sets {8}, {16}, {8, 4},
+// {6, 4}, the 12- and 20-wide engines, the generic fallback of a radix-32
+// schedule with other radices), schedules that are not a factorisation of the
+// length are refused, and a step runs afterwards
+int run_plans() {
+    struct Case { int variant, axis; std::vector<int32_t> rad; int want; };
+    const Case cases[] = {
+        {1, 2, {32}, KW_OK},          {1, 2, {8, 4}, KW_OK},      {1, 2, {16, 2}, KW_OK},
+        {1, 1, {4, 4, 2}, KW_OK},     {1, 0, {16}, KW_OK},        {1, 0, {8, 2}, KW_OK},
+        {1, 2, {8, 8}, KW_EINVAL},    {1, 1, {3, 11}, KW_EINVAL},
+        {0, 2, {6, 6}, KW_OK},        {0, 0, {6, 4}, KW_OK},      {0, 1, {10, 4}, KW_OK},
+        {0, 2, {12, 3}, KW_OK},       {0, 0, {24}, KW_OK},        {0, 2, {5, 7}, KW_EINVAL},
+        {2, 2, {10, 5}, KW_OK},       {2, 1, {15, 3}, KW_OK},       {2, 1, {5, 9}, KW_EINVAL},
+    };
+    for (const Case &c : cases) {
+        Inputs in;
+        make_inputs(c.variant, in);
+        Buffer ws(kw_workspace_size(&in.grid, &in.medium, &in.source, &in.sensor));
+        kw_sim *sim = nullptr;
+        EXPECT(kw_create(&in.grid, &in.medium, &in.source, &in.sensor, ws.p, ws.n, nullptr, &sim) == KW_OK,
+               "create: %s", kw_last_error());
+        const int rc = kw_set_plan(sim, c.axis, c.rad.data(), (int32_t)c.rad.size(), 0);
+        EXPECT(rc == c.want, "variant %d axis %d: set_plan returned %d, expected %d (%s)", c.variant,
+               c.axis, rc, c.want, kw_last_error());
+        EXPECT(kw_step(sim, 1) == KW_OK, "step after set_plan: %s", kw_last_error());
+        EXPECT(kw_destroy(sim) == KW_OK, "destroy");
+    }
+    // a 32-wide schedule with a smaller radix runs on the generic engine
+    {
+        Inputs in;
+        make_inputs(1, in);
+        in.grid.nz = 64;
+        in.npts = (size_t)in.grid.nx * in.grid.ny * in.grid.nz;
+        Buffer ws(kw_workspace_size(&in.grid, &in.medium, &in.source, &in.sensor));
+        kw_sim *sim = nullptr;
+        EXPECT(kw_create(&in.grid, &in.medium, &in.source, &in.sensor, ws.p, ws.n, nullptr, &sim) == KW_OK,
+               "create 32x32x64: %s", kw_last_error());
+        const int32_t r[2] = {32, 2};
+        EXPECT(kw_set_plan(sim, 2, r, 2, 0) == KW_OK, "schedule 32.2: %s", kw_last_error());
+        EXPECT(kw_step(sim, 1) == KW_OK, "step");
+        EXPECT(kw_destroy(sim) == KW_OK, "destroy");
+    }
+    std::printf("plans ok\n");
+    return 0;
+}
+
 }  // namespace
 
 int main(int argc, char **argv) {
     const char *mode = argc > 1 ? argv[1] : "threads";
     if (!std::strcmp(mode, "threads")) return run_threads();
     if (!std::strcmp(mode, "errors")) return run_errors();
+    if (!std::strcmp(mode, "plans")) return run_plans();
     std::printf("unknown mode %s\n", mode);
     return 2;
 }

@@ -6,8 +6,10 @@ of the kernel launchers (tests/native/hip_host_stub.cpp: "device memory" is
 host memory, copies are memcpy, fills write their values).  The driver
 (tests/native/engine_host_test.cpp) checks that kw_prepare,
 kw_create_prepared and kw_create running in 8 threads at once leave exactly
-the workspace bytes of a serial run, and that failing device calls return
-their status unchanged (kw_gather_field of the pressure included)."""
+the workspace bytes of a serial run, that failing device calls return
+their status unchanged (kw_gather_field of the pressure included), and that
+kw_set_plan accepts a schedule for every kind of FFT engine instantiation and
+refuses schedules that do not factor the length."""
 import os
 import shutil
 import subprocess
@@ -33,7 +35,7 @@ def test_engine_host_code_under_sanitizer(sanitizer, tmp_path):
     r = subprocess.run(build, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     assert r.returncode == 0, r.stdout
     env = dict(os.environ, TSAN_OPTIONS="halt_on_error=1", ASAN_OPTIONS="detect_leaks=1")
-    for mode in ("threads", "errors"):
+    for mode in ("threads", "errors", "plans"):
         r = subprocess.run([exe, mode], stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True,
                            timeout=600, env=env)
         print(r.stdout)
